@@ -1,0 +1,183 @@
+/*
+ * fuglbm.h -- C ABI of the MI355X (gfx950) implementation of the per-time-step
+ * lattice update of the fugacity-based well-balanced multicomponent lattice
+ * Boltzmann method (Soomro, Ayala, Peng & Ayala, arXiv:2212.10680).
+ *
+ * One step (Sec. III.B, steps 1-9) at every node of a periodic lattice:
+ *   moments and velocity (step 1, with the force of the previous time step),
+ *   molar densities and mole fractions (step 2), mixing rules (step 3,
+ *   App. C eqs. eqmixingrulesaSRK/eqmixingrulesbm), EOS pressure (step 4,
+ *   eqPREOS/eqSRKEOS/eqvdwEOS), ln f_i (step 5, eqfugupdatePR/SRK/VDW),
+ *   interface potential mu_I,i = -sum_j sqrt(kappa_i kappa_j) lap(rho~_j)
+ *   (step 6, eqChemPotI2/eqkappa/eq2ndder), component force
+ *   F_i = -rho~_i RT grad ln f_i - rho~_i grad mu_I,i (step 7, eqforceFugLBM,
+ *   eq1stder), well-balanced equilibrium and forcing (step 8, eqLBEMCb with
+ *   rho_0 = 0 and eqLBEMCfinal3), collision and streaming (step 9, eqLBEMCa).
+ *
+ * Conventions
+ *   - Lattice units; the caller passes the gas constant R (1 in lattice units).
+ *   - Node index n = x + nx*(y + ny*z), x fastest; D2Q9 uses nz = 1.
+ *   - Field arrays are host pointers, row-major [component or axis][node], and
+ *     are owned by the caller; the library copies in and out.
+ *   - Every call returns 0 (FL_OK) or a negative status; no exception crosses
+ *     the ABI.  fl_last_error() gives a message for the last failure of a
+ *     handle (HIP error text included for FL_EDEVICE).
+ *   - A handle is used from one host thread at a time; there is no locking.
+ *     All device work of a handle is issued on its HIP stream.
+ */
+#ifndef FUGLBM_H
+#define FUGLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FL_OK 0
+#define FL_EINVAL (-1)    /* invalid argument (see fl_create)                        */
+#define FL_EDOMAIN (-2)   /* initial state outside the EOS domain: rho~_i <= 0,
+                             rho~ b_m >= 1 or non-finite                               */
+#define FL_ENOMEM (-3)    /* device or host allocation failed / buffer too small     */
+#define FL_EDEVICE (-4)   /* HIP runtime error                                       */
+#define FL_ENUMERIC (-5)  /* a step met a node outside the EOS domain (the scheme
+                             went unstable); the state is not rolled back             */
+#define FL_ENOTCONV (-6)  /* fl_run_until reached max_steps                          */
+#define FL_EAGAIN (-7)    /* server cannot admit the request now                     */
+
+#define FL_MAX_COMP 4
+
+enum { FL_EOS_PR = 0, FL_EOS_SRK = 1, FL_EOS_VDW = 2 };
+enum { FL_D2Q9 = 0, FL_D3Q19 = 1 };
+enum { FL_BGK = 0, FL_MRT = 1 };
+enum { FL_FP64 = 0, FL_FP32POP_FP64EOS = 1 };
+
+/* One component (Sec. IV, Table tabCompProp; App. C): critical temperature and
+ * pressure, acentric factor, molar mass M (step 2) and interface strength kappa
+ * (eqs. eqChemPotI2, eqkappa). */
+typedef struct fl_component {
+    double Tc, Pc, omega, M, kappa;
+} fl_component;
+
+/* Problem statement.
+ *   ncomp       1..FL_MAX_COMP
+ *   comp        [ncomp] component constants; Tc, Pc, M > 0, kappa >= 0
+ *   kij         [ncomp*ncomp] binary interaction coefficients delta_ij of
+ *               eq. eqmixingrulesaSRK2, symmetric with zero diagonal; NULL = 0
+ *   T, R        temperature and gas constant (R = 1 in lattice units)
+ *   eos         FL_EOS_PR (App. C eqPREOS), FL_EOS_SRK, FL_EOS_VDW
+ *   lattice     FL_D2Q9 (the paper's lattice) or FL_D3Q19 (same equations, D = 3)
+ *   nx,ny,nz    periodic lattice; nz = 1 for D2Q9
+ *   collision   FL_BGK (eq. eqLBEMCa) or FL_MRT: m = M g,
+ *               m* = m - S (m - M g_eq) + (I - S/2) M F_a, with the orthogonal
+ *               moment basis of Lallemand-Luo (D2Q9) / d'Humieres (D3Q19)
+ *   tau         relaxation time, > 0.5
+ *   mrt_rates   [4] = {s_j, s_nu, s_e, s_ghost}: component momentum, traceless
+ *               stress, energy (trace) and all higher moments; NULL gives
+ *               {1/tau, 1/tau, 1, 1}; ignored for BGK
+ *   precision   FL_FP64: populations stored and collided in FP64.
+ *               FL_FP32POP_FP64EOS: populations stored and collided in FP32 (the
+ *               rest population as its offset from the initial density), EOS,
+ *               logarithms, stencils and reductions in FP64
+ *   force_time_level  0: the velocity of step 1 uses the previous step's force
+ *               (as written in Sec. III.B, step 1); 1: this step's force */
+typedef struct fl_params {
+    int ncomp;
+    const fl_component* comp;
+    const double* kij;
+    double T;
+    double R;
+    int eos;
+    int lattice;
+    int nx, ny, nz;
+    int collision;
+    double tau;
+    const double* mrt_rates;
+    int precision;
+    int force_time_level;
+} fl_params;
+
+typedef struct fl_solver fl_solver;
+
+/* Validate params; FL_EINVAL when ncomp is out of range, tau <= 0.5, a Tc, Pc or
+ * M <= 0, a kappa < 0, kij not symmetric or with a non-zero diagonal, a
+ * lattice dimension < 1 (or nz != 1 for D2Q9), an unknown enum. */
+int fl_validate(const fl_params* p);
+
+/* Device bytes a solver needs for params (both population buffers, auxiliary
+ * fields, reduction scratch).  Sets *bytes; FL_EINVAL on bad params. */
+int fl_required_bytes(const fl_params* p, size_t* bytes);
+
+/* Create a solver that allocates its own device memory and HIP stream on the
+ * current device.  The populations start at zero: call fl_set_state next. */
+int fl_create(const fl_params* p, fl_solver** out);
+
+/* Create a solver on caller-owned device memory (>= fl_required_bytes bytes,
+ * 256-byte aligned, e.g. a torch tensor) and a caller-owned hipStream_t (may be
+ * NULL for the null stream).  The caller keeps both alive until fl_destroy. */
+int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_stream,
+                  fl_solver** out);
+
+void fl_destroy(fl_solver* s);
+const char* fl_last_error(const fl_solver* s);
+const char* fl_status_string(int status);
+
+/* Lattice table used by fl_get_populations: velocities e[Q][3] (z = 0 for
+ * D2Q9) and weights w[Q]; *q receives Q.  Any output may be NULL. */
+int fl_lattice_table(int lattice, int* q, int* e, double* w);
+
+/* Set the state: rho_molar [ncomp][N] molar densities rho~_i, u [D][N] velocity
+ * (NULL = rest).  Populations become the equilibrium of eq. eqLBEMCb with the
+ * given densities and velocity, the force history is zero (the paper does not
+ * say how populations are initialised).  FL_EDOMAIN if a node has rho~_i <= 0,
+ * rho~ b_m >= 1 or a non-finite value (state unchanged). */
+int fl_set_state(fl_solver* s, const double* rho_molar, const double* u);
+
+/* Advance nsteps time steps (synchronous: returns when the work is done).
+ * FL_ENUMERIC if any step met a node outside the EOS domain. */
+int fl_step(fl_solver* s, long nsteps);
+
+/* Same, but also times each kernel of the step with HIP events on the
+ * solver's stream.  kernel_ms[k] receives the summed milliseconds of kernel k
+ * over the nsteps steps, names[k] (optional) a static name; *nkernels (in:
+ * capacity, out: count). */
+int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names,
+                  int* nkernels);
+
+/* Number of steps done since fl_set_state. */
+long fl_steps_done(const fl_solver* s);
+
+/* Macroscopic fields of the current state, any output may be NULL:
+ * rho_molar [ncomp][N]; u [D][N], the velocity of step 1 (with the stored
+ * force of the last step); p [N] EOS pressure (eqPREOS etc., no interface
+ * term); lnf [ncomp][N]. */
+int fl_get_fields(fl_solver* s, double* rho_molar, double* u, double* p, double* lnf);
+
+/* Populations g[ncomp][Q][N] in FP64 (directions in fl_lattice_table order). */
+int fl_get_populations(fl_solver* s, double* g);
+
+/* Total mass of each component, sum over nodes and directions, FP64
+ * deterministic reduction.  mass [ncomp]. */
+int fl_mass(fl_solver* s, double* mass);
+
+/* Run until the relative change rate of the densities falls below tol:
+ * r = max_i max_x |rho_i(n) - rho_i(n-K)| / (K max_x rho_i(n)), checked every
+ * K = check_every steps (FP64 reductions), at most max_steps.  Returns FL_OK
+ * when converged, FL_ENOTCONV when max_steps was reached.  steps_done and
+ * residual (may be NULL) receive the steps run and the last r. */
+int fl_run_until(fl_solver* s, double tol, long check_every, long max_steps, long* steps_done,
+                 double* residual);
+
+/* Checkpoint: raw state (populations, force history, rest-population
+ * reference, step count) as an opaque byte blob of fl_state_bytes bytes.
+ * fl_set_state_raw restores it into a solver created with the same params. */
+int fl_state_bytes(const fl_solver* s, size_t* bytes);
+int fl_get_state_raw(fl_solver* s, void* host_buf, size_t bytes);
+int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FUGLBM_H */

@@ -1,0 +1,568 @@
+// C ABI of the fugacity-based LBM solver (see include/fuglbm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fuglbm.h"
+#include "device.h"
+#include "launch.h"
+
+using fl::KParams;
+using fl::LaunchCfg;
+
+struct fl_solver {
+    fl_params prm;                         // copy (pointers re-targeted below)
+    std::vector<fl_component> comp;
+    std::vector<double> kij;
+    double mrt[4];
+    KParams kp;
+    LaunchCfg lc;
+    int D, Q, nc;
+    size_t N;
+    size_t pop_elem;                       // bytes per population value
+    // device buffers
+    void* mem = nullptr;
+    bool own_mem = false;
+    void* pop[2] = {nullptr, nullptr};
+    int cur = 0;
+    double* rt = nullptr;
+    double* lnf = nullptr;
+    double* fsum = nullptr;
+    float* rref = nullptr;
+    double* snap = nullptr;
+    double* out = nullptr;                 // (D + 1) * N scratch for field export
+    double* partial = nullptr;
+    double* red = nullptr;                 // 3*nc reduction results
+    int* err = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int* h_err = nullptr;                  // pinned host mirrors
+    double* h_red = nullptr;
+    long steps = 0;
+    bool snap_valid = false;
+    std::string last_error;
+};
+
+namespace {
+
+constexpr double kOmega[3][2] = {{0.457235529, 0.077796074},   // PR (App. C.1)
+                                 {0.4274802, 0.08664035},      // SRK
+                                 {27.0 / 64.0, 1.0 / 8.0}};    // vdW
+
+int fail(fl_solver* s, int code, const std::string& msg) {
+    if (s) s->last_error = msg;
+    return code;
+}
+
+int hip_fail(fl_solver* s, hipError_t e, const char* where) {
+    return fail(s, FL_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(s, expr)                                          \
+    do {                                                          \
+        hipError_t _e = (expr);                                   \
+        if (_e != hipSuccess) return hip_fail((s), _e, #expr);    \
+    } while (0)
+
+int lattice_dims(int lattice, int* D, int* Q) {
+    if (lattice == FL_D2Q9) { *D = 2; *Q = 9; return 0; }
+    if (lattice == FL_D3Q19) { *D = 3; *Q = 19; return 0; }
+    return -1;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t pop, rt, lnf, fsum, rref, snap, out, partial, red, err, total;
+};
+
+Layout layout_for(const fl_params* p) {
+    int D, Q;
+    lattice_dims(p->lattice, &D, &Q);
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t nc = p->ncomp;
+    const size_t es = p->precision == FL_FP64 ? 8 : 4;
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    L.pop = take(2 * nc * Q * N * es);
+    L.rt = take(nc * N * 8);
+    L.lnf = take(nc * N * 8);
+    L.fsum = take((size_t)D * N * 8);
+    L.rref = take(p->precision == FL_FP64 ? 0 : nc * N * 4);
+    L.snap = take(nc * N * 8);
+    L.out = take((size_t)(D + 1) * N * 8);
+    L.partial = take((size_t)fl::reduce_blocks((int)N) * 3 * nc * 8);
+    L.red = take(3 * nc * 8);
+    L.err = take(256);
+    L.total = off;
+    return L;
+}
+
+// Host-side EOS constants (App. C.1): a_i, b_i, alpha_i(T), (a alpha)_ij.
+void eos_constants(const fl_solver* s, KParams* kp) {
+    const fl_params& p = s->prm;
+    const int nc = p.ncomp;
+    const double Oa = kOmega[p.eos][0], Ob = kOmega[p.eos][1];
+    double aa[fl::kMaxComp];
+    for (int i = 0; i < nc; ++i) {
+        const fl_component& c = s->comp[i];
+        const double a = Oa * p.R * p.R * c.Tc * c.Tc / c.Pc;
+        kp->b[i] = Ob * p.R * c.Tc / c.Pc;
+        const double tr = p.T / c.Tc;
+        double alpha = 1.0;
+        if (p.eos == FL_EOS_PR) {
+            const double w = c.omega;
+            const double m = (w <= 0.49) ? 0.374640 + 1.54226 * w - 0.26992 * w * w
+                                         : 0.379642 + 1.48503 * w - 0.164423 * w * w + 0.016666 * w * w * w;
+            alpha = (1.0 + m * (1.0 - std::sqrt(tr))) * (1.0 + m * (1.0 - std::sqrt(tr)));
+        } else if (p.eos == FL_EOS_SRK) {
+            const double w = c.omega;
+            const double m = 0.48 + 1.574 * w - 0.176 * w * w;
+            alpha = (1.0 + m * (1.0 - std::sqrt(tr))) * (1.0 + m * (1.0 - std::sqrt(tr)));
+        }
+        aa[i] = a * alpha;
+        kp->M[i] = c.M;
+    }
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) {
+            kp->aa[i * nc + j] = std::sqrt(aa[i] * aa[j]) * (1.0 - s->kij[i * nc + j]);
+            kp->kap[i * nc + j] = std::sqrt(s->comp[i].kappa * s->comp[j].kappa);
+        }
+}
+
+// Host copy of the device EOS domain test for fl_set_state.
+bool host_in_domain(const KParams& kp, int nc, const double* rt) {
+    double r = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        if (!(rt[i] > 0.0) || !std::isfinite(rt[i])) return false;
+        r += rt[i];
+    }
+    double bm = 0.0;
+    for (int i = 0; i < nc; ++i) bm += rt[i] / r * kp.b[i];
+    return bm * r < 1.0;
+}
+
+int setup(fl_solver* s, const fl_params* p) {
+    s->prm = *p;
+    s->comp.assign(p->comp, p->comp + p->ncomp);
+    s->kij.assign((size_t)p->ncomp * p->ncomp, 0.0);
+    if (p->kij) std::memcpy(s->kij.data(), p->kij, sizeof(double) * p->ncomp * p->ncomp);
+    s->prm.comp = s->comp.data();
+    s->prm.kij = s->kij.data();
+    if (p->mrt_rates) {
+        std::memcpy(s->mrt, p->mrt_rates, sizeof(s->mrt));
+    } else {
+        s->mrt[0] = 1.0 / p->tau;
+        s->mrt[1] = 1.0 / p->tau;
+        s->mrt[2] = 1.0;
+        s->mrt[3] = 1.0;
+    }
+    s->prm.mrt_rates = s->mrt;
+    lattice_dims(p->lattice, &s->D, &s->Q);
+    s->nc = p->ncomp;
+    s->N = (size_t)p->nx * p->ny * p->nz;
+    s->pop_elem = p->precision == FL_FP64 ? 8 : 4;
+    KParams& kp = s->kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.nx = p->nx;
+    kp.ny = p->ny;
+    kp.nz = p->nz;
+    kp.N = (int)s->N;
+    kp.eos = p->eos;
+    kp.force_level = p->force_time_level;
+    kp.RT = p->R * p->T;
+    kp.lnRT = std::log(kp.RT);
+    kp.omega = 1.0 / p->tau;
+    kp.cF = 1.0 - 1.0 / (2.0 * p->tau);
+    kp.s_j = s->mrt[0];
+    kp.s_nu = s->mrt[1];
+    kp.s_e = s->mrt[2];
+    kp.s_g = s->mrt[3];
+    eos_constants(s, &kp);
+    s->lc.lattice = p->lattice;
+    s->lc.nc = p->ncomp;
+    s->lc.precision = p->precision;
+    s->lc.mrt = p->collision == FL_MRT;
+    return FL_OK;
+}
+
+int carve(fl_solver* s, void* base) {
+    const Layout L = layout_for(&s->prm);
+    char* b = (char*)base;
+    const size_t half = s->nc * s->Q * s->N * s->pop_elem;
+    s->pop[0] = b + L.pop;
+    s->pop[1] = b + L.pop + half;
+    s->rt = (double*)(b + L.rt);
+    s->lnf = (double*)(b + L.lnf);
+    s->fsum = (double*)(b + L.fsum);
+    s->rref = s->prm.precision == FL_FP64 ? nullptr : (float*)(b + L.rref);
+    s->snap = (double*)(b + L.snap);
+    s->out = (double*)(b + L.out);
+    s->partial = (double*)(b + L.partial);
+    s->red = (double*)(b + L.red);
+    s->err = (int*)(b + L.err);
+    HIP_TRY(s, hipHostMalloc((void**)&s->h_err, sizeof(int) * 4, hipHostMallocDefault));
+    HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
+    HIP_TRY(s, hipMemsetAsync(s->err, 0, 256, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->pop[0], 0, 2 * half, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->fsum, 0, (size_t)s->D * s->N * 8, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return FL_OK;
+}
+
+// Read and clear the device error flag (synchronises the stream).
+int check_err(fl_solver* s) {
+    HIP_TRY(s, hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (*s->h_err) {
+        HIP_TRY(s, hipMemsetAsync(s->err, 0, sizeof(int), s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        return fail(s, FL_ENUMERIC, "a node left the EOS domain (rho~_i <= 0, rho~ b_m >= 1 or non-finite)");
+    }
+    return FL_OK;
+}
+
+int one_step(fl_solver* s, hipEvent_t* ev) {
+    void* g = s->pop[s->cur];
+    void* gn = s->pop[1 - s->cur];
+    LaunchCfg lc = s->lc;
+    lc.stream = s->stream;
+    if (ev) HIP_TRY(s, hipEventRecord(ev[0], s->stream));
+    HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
+    if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
+    HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum));
+    if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
+    s->cur = 1 - s->cur;
+    s->steps += 1;
+    return FL_OK;
+}
+
+int reduce(fl_solver* s, bool with_snap) {
+    LaunchCfg lc = s->lc;
+    lc.stream = s->stream;
+    HIP_TRY(s, fl::launch_reduce(lc, s->kp, s->pop[s->cur], s->rref, with_snap ? s->snap : nullptr,
+                                 s->partial, s->red));
+    HIP_TRY(s, hipMemcpyAsync(s->h_red, s->red, sizeof(double) * 3 * s->nc, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fl_status_string(int st) {
+    switch (st) {
+        case FL_OK: return "ok";
+        case FL_EINVAL: return "invalid argument";
+        case FL_EDOMAIN: return "state outside the EOS domain";
+        case FL_ENOMEM: return "out of memory";
+        case FL_EDEVICE: return "HIP device error";
+        case FL_ENUMERIC: return "numerical failure during stepping";
+        case FL_ENOTCONV: return "not converged";
+        case FL_EAGAIN: return "try again";
+        default: return "unknown status";
+    }
+}
+
+int fl_validate(const fl_params* p) {
+    if (!p || !p->comp) return FL_EINVAL;
+    if (p->ncomp < 1 || p->ncomp > FL_MAX_COMP) return FL_EINVAL;
+    int D, Q;
+    if (lattice_dims(p->lattice, &D, &Q)) return FL_EINVAL;
+    if (p->eos < FL_EOS_PR || p->eos > FL_EOS_VDW) return FL_EINVAL;
+    if (p->collision != FL_BGK && p->collision != FL_MRT) return FL_EINVAL;
+    if (p->precision != FL_FP64 && p->precision != FL_FP32POP_FP64EOS) return FL_EINVAL;
+    if (p->force_time_level != 0 && p->force_time_level != 1) return FL_EINVAL;
+    if (!(p->tau > 0.5) || !(p->T > 0.0) || !(p->R > 0.0)) return FL_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return FL_EINVAL;
+    if (D == 2 && p->nz != 1) return FL_EINVAL;
+    const double N = (double)p->nx * p->ny * p->nz;
+    if (N * p->ncomp * Q >= 2147483647.0 * 4) return FL_EINVAL;
+    if (N >= 2147483647.0) return FL_EINVAL;
+    for (int i = 0; i < p->ncomp; ++i) {
+        const fl_component& c = p->comp[i];
+        if (!(c.Tc > 0) || !(c.Pc > 0) || !(c.M > 0) || !(c.kappa >= 0) || !std::isfinite(c.omega))
+            return FL_EINVAL;
+    }
+    if (p->kij)
+        for (int i = 0; i < p->ncomp; ++i)
+            for (int j = 0; j < p->ncomp; ++j) {
+                const double a = p->kij[i * p->ncomp + j], b = p->kij[j * p->ncomp + i];
+                if (!std::isfinite(a) || a != b || (i == j && a != 0.0)) return FL_EINVAL;
+            }
+    if (p->collision == FL_MRT && p->mrt_rates)
+        for (int k = 0; k < 4; ++k)
+            if (!(p->mrt_rates[k] > 0.0 && p->mrt_rates[k] < 2.0)) return FL_EINVAL;
+    return FL_OK;
+}
+
+int fl_required_bytes(const fl_params* p, size_t* bytes) {
+    const int v = fl_validate(p);
+    if (v != FL_OK) return v;
+    if (!bytes) return FL_EINVAL;
+    *bytes = layout_for(p).total;
+    return FL_OK;
+}
+
+static int create_common(const fl_params* p, void* mem, size_t bytes, void* stream, bool own, fl_solver** out) {
+    if (!out) return FL_EINVAL;
+    *out = nullptr;
+    const int v = fl_validate(p);
+    if (v != FL_OK) return v;
+    fl_solver* s = new (std::nothrow) fl_solver();
+    if (!s) return FL_ENOMEM;
+    setup(s, p);
+    const size_t need = layout_for(&s->prm).total;
+    if (own) {
+        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete s; return FL_EDEVICE; }
+        s->own_stream = true;
+        e = hipMalloc(&s->mem, need);
+        if (e != hipSuccess) {
+            hipStreamDestroy(s->stream);
+            delete s;
+            (void)hipGetLastError();
+            return FL_ENOMEM;
+        }
+        s->own_mem = true;
+    } else {
+        if (!mem || bytes < need || ((uintptr_t)mem & 255)) { delete s; return FL_ENOMEM; }
+        s->mem = mem;
+        s->stream = (hipStream_t)stream;
+    }
+    const int c = carve(s, s->mem);
+    if (c != FL_OK) { fl_destroy(s); return c; }
+    *out = s;
+    return FL_OK;
+}
+
+int fl_create(const fl_params* p, fl_solver** out) { return create_common(p, nullptr, 0, nullptr, true, out); }
+
+int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_stream, fl_solver** out) {
+    return create_common(p, device_mem, bytes, hip_stream, false, out);
+}
+
+void fl_destroy(fl_solver* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->own_mem && s->mem) (void)hipFree(s->mem);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->h_err) (void)hipHostFree(s->h_err);
+    if (s->h_red) (void)hipHostFree(s->h_red);
+    delete s;
+}
+
+const char* fl_last_error(const fl_solver* s) { return s ? s->last_error.c_str() : "null solver"; }
+
+int fl_lattice_table(int lattice, int* q, int* e, double* w) {
+    int D, Q;
+    if (lattice_dims(lattice, &D, &Q)) return FL_EINVAL;
+    if (q) *q = Q;
+    for (int a = 0; a < Q; ++a) {
+        int ex, ey, ez;
+        double wa;
+        if (lattice == FL_D2Q9) {
+            ex = fl::Lat<0>::ex[a]; ey = fl::Lat<0>::ey[a]; ez = 0; wa = fl::Lat<0>::w[a];
+        } else {
+            ex = fl::Lat<1>::ex[a]; ey = fl::Lat<1>::ey[a]; ez = fl::Lat<1>::ez[a]; wa = fl::Lat<1>::w[a];
+        }
+        if (e) { e[3 * a] = ex; e[3 * a + 1] = ey; e[3 * a + 2] = ez; }
+        if (w) w[a] = wa;
+    }
+    return FL_OK;
+}
+
+int fl_set_state(fl_solver* s, const double* rho_molar, const double* u) {
+    if (!s || !rho_molar) return FL_EINVAL;
+    const size_t N = s->N;
+    const int nc = s->nc;
+    std::vector<double> node(nc);
+    for (size_t n = 0; n < N; ++n) {
+        for (int c = 0; c < nc; ++c) node[c] = rho_molar[(size_t)c * N + n];
+        if (!host_in_domain(s->kp, nc, node.data()))
+            return fail(s, FL_EDOMAIN, "initial state outside the EOS domain at node " + std::to_string(n));
+        if (u)
+            for (int k = 0; k < s->D; ++k)
+                if (!std::isfinite(u[(size_t)k * N + n])) return fail(s, FL_EDOMAIN, "non-finite velocity");
+    }
+    // stage densities in rt and velocity in the output scratch
+    HIP_TRY(s, hipMemcpyAsync(s->rt, rho_molar, sizeof(double) * nc * N, hipMemcpyHostToDevice, s->stream));
+    if (u) HIP_TRY(s, hipMemcpyAsync(s->out, u, sizeof(double) * s->D * N, hipMemcpyHostToDevice, s->stream));
+    LaunchCfg lc = s->lc;
+    lc.stream = s->stream;
+    s->cur = 0;
+    HIP_TRY(s, fl::launch_init(lc, s->kp, s->rt, u ? s->out : nullptr, s->pop[0], s->rref, s->fsum));
+    HIP_TRY(s, hipMemsetAsync(s->err, 0, sizeof(int), s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->steps = 0;
+    s->snap_valid = false;
+    return FL_OK;
+}
+
+int fl_step(fl_solver* s, long nsteps) {
+    if (!s || nsteps < 0) return FL_EINVAL;
+    for (long k = 0; k < nsteps; ++k) {
+        const int r = one_step(s, nullptr);
+        if (r != FL_OK) return r;
+    }
+    return check_err(s);
+}
+
+int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names, int* nkernels) {
+    if (!s || nsteps < 0 || !kernel_ms || !nkernels || *nkernels < 2) return FL_EINVAL;
+    static const char* kNames[2] = {"k_moments_eos", "k_collide_stream"};
+    const long chunk = 256;
+    std::vector<hipEvent_t> ev(3 * chunk);
+    for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
+    double acc[2] = {0.0, 0.0};
+    int rc = FL_OK;
+    for (long done = 0; done < nsteps && rc == FL_OK; done += chunk) {
+        const long m = std::min(chunk, nsteps - done);
+        for (long k = 0; k < m && rc == FL_OK; ++k) rc = one_step(s, &ev[3 * k]);
+        if (rc != FL_OK) break;
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) { rc = hip_fail(s, e, "hipStreamSynchronize"); break; }
+        for (long k = 0; k < m; ++k) {
+            float a = 0.f, b = 0.f;
+            (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+            (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+            acc[0] += a;
+            acc[1] += b;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc != FL_OK) return rc;
+    kernel_ms[0] = acc[0];
+    kernel_ms[1] = acc[1];
+    if (names) { names[0] = kNames[0]; names[1] = kNames[1]; }
+    *nkernels = 2;
+    return check_err(s);
+}
+
+long fl_steps_done(const fl_solver* s) { return s ? s->steps : -1; }
+
+int fl_get_fields(fl_solver* s, double* rho_molar, double* u, double* p, double* lnf) {
+    if (!s) return FL_EINVAL;
+    const size_t N = s->N;
+    LaunchCfg lc = s->lc;
+    lc.stream = s->stream;
+    // rt/lnf are rewritten by the next step's first kernel, so they can hold
+    // the exported densities and ln f; out holds u then p.
+    double* d_u = s->out;
+    double* d_p = s->out + (size_t)s->D * N;
+    HIP_TRY(s, fl::launch_fields(lc, s->kp, s->pop[s->cur], s->rref, s->fsum, s->rt, d_u, d_p, s->lnf));
+    if (rho_molar) HIP_TRY(s, hipMemcpyAsync(rho_molar, s->rt, sizeof(double) * s->nc * N, hipMemcpyDeviceToHost, s->stream));
+    if (u) HIP_TRY(s, hipMemcpyAsync(u, d_u, sizeof(double) * s->D * N, hipMemcpyDeviceToHost, s->stream));
+    if (p) HIP_TRY(s, hipMemcpyAsync(p, d_p, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream));
+    if (lnf) HIP_TRY(s, hipMemcpyAsync(lnf, s->lnf, sizeof(double) * s->nc * N, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return FL_OK;
+}
+
+int fl_get_populations(fl_solver* s, double* g) {
+    if (!s || !g) return FL_EINVAL;
+    const size_t N = s->N;
+    const size_t bytes = sizeof(double) * s->nc * s->Q * N;
+    double* tmp = nullptr;
+    HIP_TRY(s, hipMallocAsync((void**)&tmp, bytes, s->stream));
+    LaunchCfg lc = s->lc;
+    lc.stream = s->stream;
+    hipError_t e = fl::launch_export_pops(lc, s->kp, s->pop[s->cur], s->rref, tmp);
+    if (e == hipSuccess) e = hipMemcpyAsync(g, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+    (void)hipFreeAsync(tmp, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "fl_get_populations");
+    return FL_OK;
+}
+
+int fl_mass(fl_solver* s, double* mass) {
+    if (!s || !mass) return FL_EINVAL;
+    const int r = reduce(s, false);
+    if (r != FL_OK) return r;
+    for (int c = 0; c < s->nc; ++c) mass[c] = s->h_red[c];
+    return FL_OK;
+}
+
+int fl_run_until(fl_solver* s, double tol, long check_every, long max_steps, long* steps_done, double* residual) {
+    if (!s || check_every < 1 || max_steps < 0 || !(tol >= 0.0)) return FL_EINVAL;
+    long done = 0;
+    double res = INFINITY;
+    int rc = reduce(s, true);   // snapshot of the starting densities
+    if (rc != FL_OK) return rc;
+    while (done < max_steps) {
+        const long m = std::min(check_every, max_steps - done);
+        for (long k = 0; k < m; ++k) {
+            rc = one_step(s, nullptr);
+            if (rc != FL_OK) return rc;
+        }
+        done += m;
+        rc = check_err(s);
+        if (rc != FL_OK) break;
+        rc = reduce(s, true);
+        if (rc != FL_OK) break;
+        res = 0.0;
+        for (int c = 0; c < s->nc; ++c) {
+            const double r = s->h_red[s->nc + c] / ((double)m * s->h_red[2 * s->nc + c]);
+            if (!(r <= res)) res = r;   // NaN propagates
+        }
+        if (!std::isfinite(res)) { rc = fail(s, FL_ENUMERIC, "non-finite residual"); break; }
+        if (m == check_every && res < tol) break;
+    }
+    if (steps_done) *steps_done = done;
+    if (residual) *residual = res;
+    if (rc != FL_OK) return rc;
+    return (res < tol) ? FL_OK : FL_ENOTCONV;
+}
+
+int fl_state_bytes(const fl_solver* s, size_t* bytes) {
+    if (!s || !bytes) return FL_EINVAL;
+    *bytes = 16 + s->nc * s->Q * s->N * s->pop_elem + s->D * s->N * 8 + (s->rref ? s->nc * s->N * 4 : 0);
+    return FL_OK;
+}
+
+int fl_get_state_raw(fl_solver* s, void* host_buf, size_t bytes) {
+    size_t need;
+    if (fl_state_bytes(s, &need) != FL_OK || !host_buf || bytes < need) return FL_EINVAL;
+    char* b = (char*)host_buf;
+    const int64_t hdr[2] = {(int64_t)s->steps, (int64_t)need};
+    std::memcpy(b, hdr, 16);
+    size_t off = 16;
+    const size_t pb = s->nc * s->Q * s->N * s->pop_elem;
+    HIP_TRY(s, hipMemcpyAsync(b + off, s->pop[s->cur], pb, hipMemcpyDeviceToHost, s->stream));
+    off += pb;
+    HIP_TRY(s, hipMemcpyAsync(b + off, s->fsum, s->D * s->N * 8, hipMemcpyDeviceToHost, s->stream));
+    off += s->D * s->N * 8;
+    if (s->rref) HIP_TRY(s, hipMemcpyAsync(b + off, s->rref, s->nc * s->N * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return FL_OK;
+}
+
+int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
+    size_t need;
+    if (fl_state_bytes(s, &need) != FL_OK || !host_buf || bytes < need) return FL_EINVAL;
+    const char* b = (const char*)host_buf;
+    int64_t hdr[2];
+    std::memcpy(hdr, b, 16);
+    if ((size_t)hdr[1] != need) return fail(s, FL_EINVAL, "checkpoint size does not match this solver");
+    size_t off = 16;
+    const size_t pb = s->nc * s->Q * s->N * s->pop_elem;
+    s->cur = 0;
+    HIP_TRY(s, hipMemcpyAsync(s->pop[0], b + off, pb, hipMemcpyHostToDevice, s->stream));
+    off += pb;
+    HIP_TRY(s, hipMemcpyAsync(s->fsum, b + off, s->D * s->N * 8, hipMemcpyHostToDevice, s->stream));
+    off += s->D * s->N * 8;
+    if (s->rref) HIP_TRY(s, hipMemcpyAsync(s->rref, b + off, s->nc * s->N * 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->steps = hdr[0];
+    s->snap_valid = false;
+    return FL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+// Device building blocks of the fugacity-based well-balanced LBM update on
+// gfx950: lattice tables, the cubic-EOS log-fugacity, equilibrium, forcing and
+// collision of one component at one node.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fl {
+
+constexpr int kMaxComp = 4;
+
+enum { kPR = 0, kSRK = 1, kVDW = 2 };
+
+// Per-launch constants (passed by value as a kernel argument).
+struct KParams {
+    int nx, ny, nz;
+    int N;                      // nx*ny*nz
+    int eos;
+    int force_level;            // 0: previous step's force in u; 1: this step's
+    double RT, lnRT;
+    double omega;               // 1/tau
+    double cF;                  // 1 - 1/(2 tau)
+    double s_j, s_nu, s_e, s_g; // MRT rates
+    double b[kMaxComp];
+    double M[kMaxComp];
+    double aa[kMaxComp * kMaxComp];   // (a alpha)_ij
+    double kap[kMaxComp * kMaxComp];  // kappa_ij = sqrt(kappa_i kappa_j)
+};
+
+// ---------------------------------------------------------------- lattices
+// Directions are stored opposite pairs next to each other after the rest one.
+template <int LAT>
+struct Lat;
+
+template <>
+struct Lat<0> {  // D2Q9
+    static constexpr int D = 2;
+    static constexpr int Q = 9;
+    static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int ey[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+template <>
+struct Lat<1> {  // D3Q19
+    static constexpr int D = 3;
+    static constexpr int Q = 19;
+    static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                     1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+// ------------------------------------------------------------------- EOS
+// Steps 3-5 at one node from the molar densities rt[i] (App. C mixing rules,
+// eqPREOS/eqSRKEOS/eqvdwEOS, and ln f_i of eqfugupdatePR/SRK/VDW).  The
+// density-explicit ln f is evaluated in the algebraically identical form
+//   ln f_i = ln(rho~_i RT) - log1p(-eta) + (b_i/b_m)(Z-1)
+//            + C (b_i/b_m - 2 s_i/(a alpha)_m) L,   eta = b_m rho~,
+// with L = log1p(2 sqrt2 eta / (1 + (1-sqrt2) eta)) for PR and log1p(eta) for
+// SRK: ln((v-b_m)/RT) and the ratio of the last logarithm are rewritten around
+// 1 so that dilute vapor keeps full FP64 precision.  Returns false outside the
+// domain (rho~_i <= 0, eta >= 1, non-finite).
+template <int NC>
+__device__ __forceinline__ bool eos_lnf(const KParams& kp, const double (&rt)[NC],
+                                        double (&lnf)[NC], double* p_out) {
+    constexpr double kSqrt2 = 1.4142135623730951;
+    double r = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        r += rt[i];
+        ok = ok && (rt[i] > 0.0);
+    }
+    const double inv = 1.0 / r;
+    double x[NC], s[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) x[i] = rt[i] * inv;
+    double bm = 0.0, am = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) bm += x[i] * kp.b[i];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        double si = 0.0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) si += x[j] * kp.aa[i * NC + j];
+        s[i] = si;
+        am += x[i] * si;
+    }
+    const double eta = bm * r;
+    ok = ok && (eta < 1.0) && (r < 1e300);
+    const double RT = kp.RT;
+    const double l1 = log1p(-eta);             // ln(1 - eta)
+    double zm1, l2, coef, p;
+    if (kp.eos == kPR) {
+        const double den = 1.0 + 2.0 * eta - eta * eta;
+        zm1 = eta / (1.0 - eta) - am * r / (RT * den);
+        l2 = log1p(2.0 * kSqrt2 * eta / (1.0 + (1.0 - kSqrt2) * eta));
+        coef = am / (2.0 * kSqrt2 * bm * RT);
+        p = r * RT / (1.0 - eta) - am * r * r / den;
+    } else if (kp.eos == kSRK) {
+        const double den = 1.0 + eta;
+        zm1 = eta / (1.0 - eta) - am * r / (RT * den);
+        l2 = log1p(eta);
+        coef = am / (bm * RT);
+        p = r * RT / (1.0 - eta) - am * r * r / den;
+    } else {
+        zm1 = 0.0;
+        l2 = 0.0;
+        coef = 0.0;
+        p = r * RT / (1.0 - eta) - am * r * r;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        double l = log(rt[i]) + kp.lnRT - l1;
+        if (kp.eos == kVDW)
+            l += kp.b[i] * r / (1.0 - eta) - 2.0 * s[i] * r / RT;
+        else
+            l += kp.b[i] / bm * zm1 + coef * (kp.b[i] / bm - 2.0 * s[i] / am) * l2;
+        lnf[i] = l;
+        ok = ok && (l == l);
+    }
+    if (p_out) *p_out = p;
+    return ok;
+}
+
+// --------------------------------------------- equilibrium, forcing, collision
+// Scalars of one component at one node, in the collision precision T.
+template <typename T>
+struct CompState {
+    T rho;        // rho_i (mass density)
+    T ux, uy, uz; // barycentric velocity (step 1)
+    T Fx, Fy, Fz; // component force F_i (step 7)
+    T Gx, Gy, Gz; // grad rho_i (eq1stder)
+};
+
+// Well-balanced equilibrium without its rest-population density term
+// (eq. eqLBEMCb, rho_0 = rho_0,i = 0): w_a rho [3 e.u + 9/2 (e.u)^2 - 3/2 u.u].
+// The rest population adds rho_i itself.
+template <typename L, typename T, int A>
+__device__ __forceinline__ T geq_shape(const CompState<T>& c, T uu) {
+    constexpr T ex = L::ex[A], ey = L::ey[A], ez = L::ez[A];
+    const T eu = ex * c.ux + ey * c.uy + ez * c.uz;
+    return T(L::w[A]) * c.rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+}
+
+// Forcing term of eq. eqLBEMCfinal3 with c_s^2 = 1/3:
+// w_a [F.((e-u)/cs2 + (u.e) e/cs4) + grad rho.(-u + (u.e) e/cs2 + (e^2/cs2 - D) u / 2)].
+template <typename L, typename T, int A>
+__device__ __forceinline__ T forcing(const CompState<T>& c, T uF, T uG) {
+    constexpr T ex = L::ex[A], ey = L::ey[A], ez = L::ez[A];
+    constexpr T e2 = ex * ex + ey * ey + ez * ez;
+    constexpr T half_term = T(-1) + T(0.5) * (T(3) * e2 - T(L::D));
+    const T eu = ex * c.ux + ey * c.uy + ez * c.uz;
+    const T eF = ex * c.Fx + ey * c.Fy + ez * c.Fz;
+    const T eG = ex * c.Gx + ey * c.Gy + ez * c.Gz;
+    return T(L::w[A]) * (T(3) * eF - T(3) * uF + T(9) * eu * eF + half_term * uG + T(3) * eu * eG);
+}
+
+template <int I, int N>
+struct Unroll {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&& f) {
+        f(std::integral_constant<int, I>{});
+        Unroll<I + 1, N>::run(f);
+    }
+};
+template <int N>
+struct Unroll<N, N> {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// Collision of one component.  gv[a] holds the stored populations (for the
+// FP32 form the rest slot holds g_0 minus the reference density, and
+// moving_sum is sum_{a != 0} g_a); out[a] receives the post-collision value in
+// the same convention.
+//   BGK (eq. eqLBEMCa): g* = g - (g - g_eq)/tau + (1 - 1/(2 tau)) F_a.
+//   MRT: g* = g + F_a - M^-1 S M v with v = g - g_eq + F_a/2.  With an
+//   orthogonal moment basis M^-1 S M = s_g I + sum_k (s_k - s_g) P_k over the
+//   momentum, traceless-stress and energy groups (P_k the orthogonal projector
+//   of group k); the conserved density row contributes nothing because
+//   sum_a v_a = 0.
+template <typename L, typename T, bool MRT, bool REST_OFFSET>
+__device__ __forceinline__ void collide(const KParams& kp, const CompState<T>& c, const T (&gv)[L::Q],
+                                        T moving_sum, T (&out)[L::Q]) {
+    constexpr int Q = L::Q;
+    const T uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+    const T uF = c.ux * c.Fx + c.uy * c.Fy + c.uz * c.Fz;
+    const T uG = c.ux * c.Gx + c.uy * c.Gy + c.uz * c.Gz;
+    T neq[Q];  // g - g_eq
+    T Fa[Q];
+    Unroll<0, Q>::run([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        const T sh = geq_shape<L, T, a>(c, uu);
+        if constexpr (a == 0) {
+            if constexpr (REST_OFFSET)
+                neq[0] = -moving_sum - sh;      // g_0 - rho - w_0 rho B_0
+            else
+                neq[0] = gv[0] - (c.rho + sh);
+        } else {
+            neq[a] = gv[a] - sh;
+        }
+        Fa[a] = forcing<L, T, a>(c, uF, uG);
+    });
+    if constexpr (!MRT) {
+        const T om = T(kp.omega), cf = T(kp.cF);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) out[a] = gv[a] - om * neq[a] + cf * Fa[a];
+    } else {
+        const T sg = T(kp.s_g);
+        T v[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) v[a] = neq[a] + T(0.5) * Fa[a];
+        // group moments of v
+        T jx = 0, jy = 0, jz = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0, me = 0;
+        Unroll<0, Q>::run([&](auto ai) {
+            constexpr int a = decltype(ai)::value;
+            constexpr T ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
+            constexpr T e2 = ex * ex + ey * ey + ez * ez;
+            jx += ex * v[a];
+            jy += ey * v[a];
+            jz += ez * v[a];
+            if constexpr (L::D == 2) {
+                m1 += (ex * ex - ey * ey) * v[a];
+                m2 += (ex * ey) * v[a];
+                me += (T(-4) + T(3) * e2) * v[a];
+            } else {
+                m1 += (T(3) * ex * ex - e2) * v[a];
+                m2 += (ey * ey - ez * ez) * v[a];
+                m3 += (ex * ey) * v[a];
+                m4 += (ey * ez) * v[a];
+                m5 += (ex * ez) * v[a];
+                me += (T(19) * e2 - T(30)) * v[a];
+            }
+        });
+        // scale by (s_k - s_g) / |row|^2
+        const T dj = T(kp.s_j) - sg, dn = T(kp.s_nu) - sg, de = T(kp.s_e) - sg;
+        if constexpr (L::D == 2) {
+            jx *= dj / T(6); jy *= dj / T(6);
+            m1 *= dn / T(4); m2 *= dn / T(4);
+            me *= de / T(36);
+        } else {
+            jx *= dj / T(10); jy *= dj / T(10); jz *= dj / T(10);
+            m1 *= dn / T(36); m2 *= dn / T(12); m3 *= dn / T(4); m4 *= dn / T(4); m5 *= dn / T(4);
+            me *= de / T(2394);
+        }
+        Unroll<0, Q>::run([&](auto ai) {
+            constexpr int a = decltype(ai)::value;
+            constexpr T ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
+            constexpr T e2 = ex * ex + ey * ey + ez * ez;
+            T corr = ex * jx + ey * jy + ez * jz;
+            if constexpr (L::D == 2) {
+                corr += (ex * ex - ey * ey) * m1 + (ex * ey) * m2 + (T(-4) + T(3) * e2) * me;
+            } else {
+                corr += (T(3) * ex * ex - e2) * m1 + (ey * ey - ez * ez) * m2 + (ex * ey) * m3 +
+                        (ey * ez) * m4 + (ex * ez) * m5 + (T(19) * e2 - T(30)) * me;
+            }
+            out[a] = gv[a] + Fa[a] - sg * v[a] - corr;
+        });
+    }
+}
+
+}  // namespace fl

@@ -1,0 +1,492 @@
+// HIP kernels of the per-step update and its auxiliary passes (gfx950).
+//
+// Layout in HBM (structure of arrays, node index n = x + nx*(y + ny*z)):
+//   populations  g[c][a][n]   (P = double, or float in the FP32 form where the
+//                             rest slot a = 0 holds g_0 minus rref[c][n])
+//   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64)
+//   fsum[k][n]                sum_i F_i of the previous step (FP64)
+//   rref[c][n]                rest-population reference (FP32 form only)
+//
+// Step = k_moments_eos (steps 1-5: reads every population once, writes rt and
+// ln f) followed by k_collide_stream (steps 6-9: reads the node's populations,
+// the rt stencil of Manhattan radius 2 and the ln f stencil of radius 1, and
+// pushes the collided populations to x + e_a of the other buffer).
+#include "device.h"
+#include "launch.h"
+
+namespace fl {
+
+template <typename L, int NC, typename P>
+__device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t N, P (&gv)[NC][L::Q]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) gv[c][a] = g[(size_t)(c * L::Q + a) * N + n];
+}
+
+// rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
+template <typename L, int NC, typename P>
+__device__ __forceinline__ void densities(const P (&gv)[NC][L::Q], const float* __restrict__ rref, int n,
+                                          size_t N, double (&rho)[NC], double (&moving)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double m = 0.0;
+#pragma unroll
+        for (int a = 1; a < L::Q; ++a) m += (double)gv[c][a];
+        double r0 = (double)gv[c][0];
+        if constexpr (sizeof(P) == 4) r0 += (double)rref[(size_t)c * N + n];
+        moving[c] = m;
+        rho[c] = r0 + m;
+    }
+}
+
+__device__ __forceinline__ int wrapi(int v, int m) {
+    v %= m;
+    return v < 0 ? v + m : v;
+}
+
+// ----------------------------------------------------------------- step 1-5
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __restrict__ g,
+                                                     const float* __restrict__ rref,
+                                                     double* __restrict__ rt, double* __restrict__ lnf,
+                                                     int* __restrict__ err) {
+    using L = Lat<LAT>;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const size_t N = kp.N;
+    P gv[NC][L::Q];
+    load_pops<L, NC, P>(g, n, N, gv);
+    double rho[NC], mov[NC], r[NC], lf[NC];
+    densities<L, NC, P>(gv, rref, n, N, rho, mov);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        r[c] = rho[c] / kp.M[c];
+        rt[(size_t)c * N + n] = r[c];
+    }
+    const bool ok = eos_lnf<NC>(kp, r, lf, nullptr);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lnf[(size_t)c * N + n] = lf[c];
+    if (!ok) atomicOr(err, 1);
+}
+
+// ---------------------------------------------------------------- step 6-9
+template <int LAT, int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __restrict__ g,
+                                                        P* __restrict__ gn,
+                                                        const float* __restrict__ rref,
+                                                        const double* __restrict__ rt,
+                                                        const double* __restrict__ lnf,
+                                                        double* __restrict__ fsum) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    using T = P;  // collision precision
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const size_t N = kp.N;
+    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const int x = n % nx;
+    const int t = n / nx;
+    const int y = t % ny;
+    const int z = t / ny;
+    int X[5], Y[5], Z[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        X[d + 2] = wrapi(x + d, nx);
+        Y[d + 2] = wrapi(y + d, ny);
+        Z[d + 2] = (D == 3) ? wrapi(z + d, nz) : 0;
+    }
+    auto idx = [&](int dx, int dy, int dz) { return X[dx + 2] + nx * (Y[dy + 2] + ny * Z[dz + 2]); };
+    auto unit = [](int k, int s, int& dx, int& dy, int& dz) {
+        dx = (k == 0) ? s : 0;
+        dy = (k == 1) ? s : 0;
+        dz = (k == 2) ? s : 0;
+    };
+
+    // step 6: Laplacian of rho~_j at the 2D neighbours, then mu_I,i there
+    double mu[NC][2 * D];
+    double rc[NC];   // rho~_i at the node
+    double rnb[NC][2 * D];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) rc[j] = rt[(size_t)j * N + n];
+    double lap[NC][2 * D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            int cx, cy, cz;
+            unit(k, s == 0 ? 1 : -1, cx, cy, cz);
+            const int ci = idx(cx, cy, cz);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const double* r = rt + (size_t)j * N;
+                const double r0 = r[ci];
+                rnb[j][2 * k + s] = r0;
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    int mx, my, mz;
+                    unit(m, 1, mx, my, mz);
+                    acc += r[idx(cx + mx, cy + my, cz + mz)] - 2.0 * r0 + r[idx(cx - mx, cy - my, cz - mz)];
+                }
+                lap[j][2 * k + s] = acc;
+            }
+        }
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int q = 0; q < 2 * D; ++q) {
+            double m = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) m -= kp.kap[i * NC + j] * lap[j][q];
+            mu[i][q] = m;
+        }
+
+    // step 7: F_i = -rho~_i [RT D(ln f_i) + D(mu_I,i)], and grad rho_i
+    double F[NC][3], G[NC][3];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const double* lf = lnf + (size_t)i * N;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            F[i][k] = 0.0;
+            G[i][k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            int px, py, pz;
+            unit(k, 1, px, py, pz);
+            const double dl = (lf[idx(px, py, pz)] - lf[idx(-px, -py, -pz)]) / 2.0;
+            const double dm = (mu[i][2 * k] - mu[i][2 * k + 1]) / 2.0;
+            F[i][k] = -rc[i] * (kp.RT * dl + dm);
+            G[i][k] = kp.M[i] * (rnb[i][2 * k] - rnb[i][2 * k + 1]) / 2.0;
+        }
+    }
+
+    // step 1 (again, for this node): moments and velocity
+    P gv[NC][Q];
+    load_pops<L, NC, P>(g, n, N, gv);
+    double rho[NC], mov[NC];
+    densities<L, NC, P>(gv, rref, n, N, rho, mov);
+    double rtot = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        rtot += rho[c];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            j[0] += (double)gv[c][a] * L::ex[a];
+            j[1] += (double)gv[c][a] * L::ey[a];
+            j[2] += (double)gv[c][a] * L::ez[a];
+        }
+    }
+    double Fs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fs[k] += F[i][k];
+    double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double fk = kp.force_level ? Fs[k] : fsum[(size_t)k * N + n];
+        u[k] = (j[k] + 0.5 * fk) / rtot;
+    }
+
+    // steps 8-9 per component, push streaming into the other buffer
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        CompState<T> cs;
+        cs.rho = T(rho[c]);
+        cs.ux = T(u[0]); cs.uy = T(u[1]); cs.uz = T(u[2]);
+        cs.Fx = T(F[c][0]); cs.Fy = T(F[c][1]); cs.Fz = T(F[c][2]);
+        cs.Gx = T(G[c][0]); cs.Gy = T(G[c][1]); cs.Gz = T(G[c][2]);
+        T out[Q];
+        collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])] = out[a];
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = Fs[k];
+}
+
+// ------------------------------------------------------------ initial state
+// g = g_eq(rho_i, u) (eq. eqLBEMCb), zero force history.
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restrict__ rho_molar,
+                                              const double* __restrict__ uin, P* __restrict__ g,
+                                              float* __restrict__ rref, double* __restrict__ fsum) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const size_t N = kp.N;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (uin)
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = uin[(size_t)k * N + n];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double rho = rho_molar[(size_t)c * N + n] * kp.M[c];
+        double ref = 0.0;
+        if constexpr (sizeof(P) == 4) {
+            const float rf = (float)rho;
+            rref[(size_t)c * N + n] = rf;
+            ref = (double)rf;
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const double eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
+            double ge = L::w[a] * rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+            if (a == 0) ge += rho - ref;
+            g[(size_t)(c * Q + a) * N + n] = (P)ge;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = 0.0;
+}
+
+// ------------------------------------------------------------ output fields
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_fields(KParams kp, const P* __restrict__ g,
+                                                const float* __restrict__ rref,
+                                                const double* __restrict__ fsum,
+                                                double* __restrict__ rho_molar, double* __restrict__ uout,
+                                                double* __restrict__ pout, double* __restrict__ lnf) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const size_t N = kp.N;
+    P gv[NC][Q];
+    load_pops<L, NC, P>(g, n, N, gv);
+    double rho[NC], mov[NC], r[NC], lf[NC];
+    densities<L, NC, P>(gv, rref, n, N, rho, mov);
+    double rtot = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        r[c] = rho[c] / kp.M[c];
+        rho_molar[(size_t)c * N + n] = r[c];
+        rtot += rho[c];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            j[0] += (double)gv[c][a] * L::ex[a];
+            j[1] += (double)gv[c][a] * L::ey[a];
+            j[2] += (double)gv[c][a] * L::ez[a];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) uout[(size_t)k * N + n] = (j[k] + 0.5 * fsum[(size_t)k * N + n]) / rtot;
+    double p;
+    eos_lnf<NC>(kp, r, lf, &p);
+    pout[n] = p;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lnf[(size_t)c * N + n] = lf[c];
+}
+
+// Populations as FP64 [c][a][n] (rest slot with its reference added back).
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_export_pops(KParams kp, const P* __restrict__ g,
+                                                     const float* __restrict__ rref, double* __restrict__ out) {
+    using L = Lat<LAT>;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const size_t N = kp.N;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            double v = (double)g[(size_t)(c * L::Q + a) * N + n];
+            if constexpr (sizeof(P) == 4)
+                if (a == 0) v += (double)rref[(size_t)c * N + n];
+            out[(size_t)(c * L::Q + a) * N + n] = v;
+        }
+}
+
+// ---------------------------------------------------------------- reductions
+// Block-level deterministic reduction: each block writes NC partial sums of
+// rho_i (mass) and, when snap != nullptr, NC maxima of |rho_i - snap_i| and of
+// rho_i, then updates the snapshot.  A single-block pass combines partials in
+// block order.
+constexpr int kRedBlock = 256;
+
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(kRedBlock) void k_reduce_partials(KParams kp, const P* __restrict__ g,
+                                                               const float* __restrict__ rref,
+                                                               double* __restrict__ snap,
+                                                               double* __restrict__ partial) {
+    using L = Lat<LAT>;
+    __shared__ double sh[3 * NC][kRedBlock];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t N = kp.N;
+    double rho[NC] = {}, dif[NC] = {}, mx[NC] = {};
+    if (n < kp.N) {
+        P gv[NC][L::Q];
+        load_pops<L, NC, P>(g, n, N, gv);
+        double mov[NC];
+        densities<L, NC, P>(gv, rref, n, N, rho, mov);
+        if (snap) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double old = snap[(size_t)c * N + n];
+                dif[c] = fabs(rho[c] - old);
+                mx[c] = fabs(rho[c]);
+                snap[(size_t)c * N + n] = rho[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        sh[c][threadIdx.x] = rho[c];
+        sh[NC + c][threadIdx.x] = dif[c];
+        sh[2 * NC + c][threadIdx.x] = mx[c];
+    }
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+                sh[NC + c][threadIdx.x] = fmax(sh[NC + c][threadIdx.x], sh[NC + c][threadIdx.x + s]);
+                sh[2 * NC + c][threadIdx.x] = fmax(sh[2 * NC + c][threadIdx.x], sh[2 * NC + c][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3 * NC) partial[(size_t)blockIdx.x * 3 * NC + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <int NC>
+__global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __restrict__ partial, int nblocks,
+                                                            double* __restrict__ out) {
+    __shared__ double sh[3 * NC][kRedBlock];
+    double acc[3 * NC] = {};
+    // each thread folds a contiguous run of blocks in order
+    const int per = (nblocks + kRedBlock - 1) / kRedBlock;
+    const int b0 = threadIdx.x * per;
+    for (int b = b0; b < b0 + per && b < nblocks; ++b)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            acc[c] += partial[(size_t)b * 3 * NC + c];
+            acc[NC + c] = fmax(acc[NC + c], partial[(size_t)b * 3 * NC + NC + c]);
+            acc[2 * NC + c] = fmax(acc[2 * NC + c], partial[(size_t)b * 3 * NC + 2 * NC + c]);
+        }
+#pragma unroll
+    for (int q = 0; q < 3 * NC; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+                sh[NC + c][threadIdx.x] = fmax(sh[NC + c][threadIdx.x], sh[NC + c][threadIdx.x + s]);
+                sh[2 * NC + c][threadIdx.x] = fmax(sh[2 * NC + c][threadIdx.x], sh[2 * NC + c][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3 * NC) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------ launchers
+static inline dim3 grid_for(int N, int block) { return dim3((N + block - 1) / block); }
+
+template <typename T>
+struct Tag {
+    using type = T;
+};
+
+// Calls f(lattice, components, population type) with compile-time values.
+template <typename F>
+void dispatch(int lattice, int nc, int precision, F&& f) {
+    auto run_nc = [&](auto latc, auto ncc) {
+        if (precision == 0)
+            f(latc, ncc, Tag<double>{});
+        else
+            f(latc, ncc, Tag<float>{});
+    };
+    auto run_lat = [&](auto latc) {
+        switch (nc) {
+            case 1: run_nc(latc, std::integral_constant<int, 1>{}); break;
+            case 2: run_nc(latc, std::integral_constant<int, 2>{}); break;
+            case 3: run_nc(latc, std::integral_constant<int, 3>{}); break;
+            default: run_nc(latc, std::integral_constant<int, 4>{}); break;
+        }
+    };
+    if (lattice == 0)
+        run_lat(std::integral_constant<int, 0>{});
+    else
+        run_lat(std::integral_constant<int, 1>{});
+}
+
+#define FL_TYPES                                  \
+    constexpr int LAT = decltype(latc)::value;    \
+    constexpr int NC = decltype(ncc)::value;      \
+    using P = typename decltype(pt)::type
+
+hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                              double* rt, double* lnf, int* err) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_moments_eos<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
+            kp, (const P*)g, rref, rt, lnf, err);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                 const float* rref, const double* rt, const double* lnf, double* fsum) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        if (lc.mrt)
+            k_collide_stream<LAT, NC, P, true><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, fsum);
+        else
+            k_collide_stream<LAT, NC, P, false><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, fsum);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
+                       void* g, float* rref, double* fsum) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_init<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, rho_molar, u, (P*)g, rref, fsum);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                         const double* fsum, double* rho_molar, double* u, double* p, double* lnf) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_fields<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, (const P*)g, rref, fsum,
+                                                                          rho_molar, u, p, lnf);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_export_pops(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                              double* out) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_export_pops<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, (const P*)g, rref, out);
+    });
+    return hipGetLastError();
+}
+
+int reduce_blocks(int N) { return (N + kRedBlock - 1) / kRedBlock; }
+
+hipError_t launch_reduce(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                         double* snap, double* partial, double* out) {
+    const int nb = reduce_blocks(kp.N);
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_reduce_partials<LAT, NC, P><<<nb, kRedBlock, 0, lc.stream>>>(kp, (const P*)g, rref, snap, partial);
+        k_reduce_final<NC><<<1, kRedBlock, 0, lc.stream>>>(partial, nb, out);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace fl

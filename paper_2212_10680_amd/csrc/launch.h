@@ -1,0 +1,34 @@
+// Host-side launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace fl {
+
+struct LaunchCfg {
+    int lattice;    // 0 D2Q9, 1 D3Q19
+    int nc;         // components
+    int precision;  // 0 FP64, 1 FP32 populations
+    bool mrt;
+    hipStream_t stream;
+};
+
+hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                              double* rt, double* lnf, int* err);
+hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                 const float* rref, const double* rt, const double* lnf, double* fsum);
+hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
+                       void* g, float* rref, double* fsum);
+hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                         const double* fsum, double* rho_molar, double* u, double* p, double* lnf);
+hipError_t launch_export_pops(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                              double* out);
+// Deterministic reduction: out[0..nc) = sum_x rho_i, out[nc..2nc) = max |rho_i - snap_i|
+// (snap updated; zero when snap is null), out[2nc..3nc) = max rho_i.
+hipError_t launch_reduce(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
+                         double* snap, double* partial, double* out);
+int reduce_blocks(int N);
+
+}  // namespace fl

@@ -1,0 +1,297 @@
+"""GPU (HIP, gfx950) parity with the FP64 oracle, through the C ABI.
+
+FP64 path: populations and fields element by element after 1, 10 and 1000
+steps, bar 1e-12 relative (oracle transients are "parity unpinned" beyond the
+oracle itself, so the bar is rounding-level agreement).  FP32-population form:
+densities within 1e-4 relative of the FP64 oracle (the stated tolerance for the
+precision form).  Sizes span several 256-node blocks and a ragged tail.
+"""
+import numpy as np
+import pytest
+
+from paper_2212_10680_amd import fuglbm as F
+from paper_2212_10680_amd import workloads as wl
+
+from _util import direction_map, oracle_for, rel, smooth_3d_field
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-12
+FP32_BAR = 1e-4
+
+
+def announce(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def make_pair(w, precision="fp64", rho=None, u=None, force_level=0, eos="PR", mrt_rates=None):
+    if rho is None:
+        rho, u = wl.initial_field(w)
+    nc, D = w.ncomp, w.D
+    rho = rho.reshape(nc, -1)
+    u = None if u is None else u.reshape(D, -1)
+    S = None
+    if mrt_rates is not None:
+        from oracle import lattice as olat
+        _, groups = olat.mrt_basis(w.lattice)
+        table = {"rho": 1.0 / w.tau, "j": mrt_rates[0], "nu": mrt_rates[1], "e": mrt_rates[2],
+                 "ghost": mrt_rates[3]}
+        S = np.array([table[g] for g in groups])
+    o = oracle_for(w, eos=eos, force_level=force_level, mrt_S=S)
+    o.init(rho, u)
+    p = F.Params.from_workload(w, precision=precision, force_time_level=force_level, eos=eos,
+                               mrt_rates=mrt_rates)
+    s = F.Solver(p)
+    s.set_state(rho, u)
+    return o, s
+
+
+def compare(o, s, w, bar, what=""):
+    e, _ = F.lattice_table(w.lattice)
+    perm = direction_map(w.lattice, e)
+    g_gpu = s.populations()
+    g_orc = o.g[:, perm, :]
+    eg = rel(g_gpu, g_orc)
+    fo = o.fields()
+    fs = s.fields()
+    er = rel(fs["rho_molar"], fo["rho_molar"])
+    eu = float(np.max(np.abs(fs["u"] - fo["u"])) / max(np.max(np.abs(fo["u"])), 1e-12))
+    ep = rel(fs["p"], fo["p"])
+    el = rel(fs["lnf"], fo["lnf"])
+    print(f"  {what} steps={o.steps}: pops {eg:.2e} rho {er:.2e} u {eu:.2e} p {ep:.2e} lnf {el:.2e}",
+          flush=True)
+    assert eg < bar and er < bar and ep < bar and el < bar, (eg, er, ep, el)
+    assert eu < max(bar * 1e3, 1e-9) if bar < 1e-6 else eu < 1e-2
+    return eg
+
+
+CASES_FP64 = [
+    # name, workload, shape, steps schedule
+    ("binary D2Q9 BGK noisy 61x7", "binary_slab_2d", (61, 7), (1, 9, 990)),
+    ("binary D2Q9 BGK 64x8 (cfg0 shape)", "binary_slab_2d", (64, 8), (1, 9, 990)),
+    ("ternary D2Q9 MRT droplet 48x40", "ternary_droplet_2d", (48, 40), (1, 9, 190)),
+]
+
+
+@pytest.mark.parametrize("name,wname,shape,sched", CASES_FP64)
+def test_fp64_parity_2d(name, wname, shape, sched):
+    w = wl.WORKLOADS[wname].scaled(shape)
+    announce(name)
+    o, s = make_pair(w)
+    for k in sched:
+        o.run(k)
+        s.step(k)
+        compare(o, s, w, FP64_BAR, name)
+
+
+@pytest.mark.parametrize("coll", ["BGK", "MRT"])
+@pytest.mark.parametrize("wname,shape", [("binary_slab_3d", (21, 10, 6)),
+                                         ("ternary_droplets_3d", (20, 12, 9))])
+def test_fp64_parity_3d(coll, wname, shape):
+    w = wl.WORKLOADS[wname].scaled(shape)
+    w.collision = coll
+    if wname == "ternary_droplets_3d":
+        w.geometry = "slab"          # smooth 3-D field (see smooth_3d_field)
+        w.u0 = 0.0
+    rho, u = smooth_3d_field(w)
+    announce(f"{wname} D3Q19 {coll} {shape}")
+    o, s = make_pair(w, rho=rho, u=u)
+    # short runs: D3Q19 fields grow high-wavenumber modes, which amplify any
+    # rounding difference by about x200 every further 10 steps
+    for k in (1, 9):
+        o.run(k)
+        s.step(k)
+        compare(o, s, w, FP64_BAR, f"3d {coll}")
+
+
+def smooth_vapor_field(w, rho_V, amp=0.05):
+    """Single-phase vapor-like field with smooth, component-shifted modulations:
+    exercises every term of the step without the interface instabilities."""
+    nx, ny = w.shape[0], w.shape[1]
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = []
+    for i, r in enumerate(rho_V):
+        out.append(r * (1 + amp * np.sin(2 * np.pi * (x / nx + 0.1 * i))
+                        + 0.6 * amp * np.cos(2 * np.pi * (y / ny + 0.2 * i))))
+    return np.ascontiguousarray(np.stack(out)[:, None])
+
+
+@pytest.mark.parametrize("variant", ["force_level_1", "SRK", "VDW", "mrt_all_rates"])
+def test_fp64_parity_variants(variant):
+    w = wl.WORKLOADS["binary_slab_2d"].scaled((40, 6))
+    kw = {}
+    if variant == "force_level_1":
+        kw["force_level"] = 1
+    elif variant in ("SRK", "VDW"):
+        kw["eos"] = variant
+    else:
+        w.collision = "MRT"
+        kw["mrt_rates"] = [1.1, 0.9, 1.2, 1.3]
+    _, rV, _ = w.phase_densities()
+    rho = smooth_vapor_field(w, rV)
+    announce(f"variant {variant}")
+    o, s = make_pair(w, rho=rho, **kw)
+    for k in (1, 99):
+        o.run(k)
+        s.step(k)
+        compare(o, s, w, FP64_BAR, variant)
+
+
+@pytest.mark.parametrize("nc", [1, 4])
+def test_fp64_parity_component_counts(nc):
+    """One component (pure fluid) and four components (the ABI maximum)."""
+    base = wl.WORKLOADS["ternary_droplet_2d"].scaled((33, 9))
+    comps, kij, T = base.thermo()
+    if nc == 1:
+        comps = [comps[2]]
+        kij = np.zeros((1, 1))
+    else:
+        extra = dict(comps[1])
+        extra["Tc"] *= 1.1
+        extra["Pc"] *= 1.05
+        comps = comps + [extra]
+        kij = np.pad(kij, ((0, 1), (0, 1)), constant_values=0.01)
+        np.fill_diagonal(kij, 0.0)
+    from oracle import lbm, thermo as th
+    mix = th.Mixture([c["Tc"] for c in comps], [c["Pc"] for c in comps], [c["omega"] for c in comps],
+                     T, kij=kij, M=[c["M"] for c in comps], kappa=[c["kappa"] for c in comps])
+    nx, ny = base.shape
+    rho = smooth_vapor_field(base, [0.3 + 0.1 * k for k in range(nc)]).reshape(nc, -1)
+    o = lbm.OracleLBM(mix, "D2Q9", (nx, ny), tau=1.0)
+    o.init(rho)
+    p = F.Params(comps, T, (nx, ny), kij=kij, tau=1.0)
+    announce(f"nc={nc}")
+    s = F.Solver(p)
+    s.set_state(rho)
+    for k in (1, 99):
+        o.run(k)
+        s.step(k)
+        compare(o, s, base, FP64_BAR, f"nc={nc}")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 5), (7, 1), (2, 3)])
+def test_degenerate_shapes(shape):
+    """Lattices thinner than the stencil (periodic images coincide)."""
+    w = wl.WORKLOADS["binary_slab_2d"].scaled(shape)
+    w.noise = 0.003
+    announce(f"degenerate {shape}")
+    rL, rV, _ = w.phase_densities()
+    rho, _ = wl.initial_field(w, rho_LV=(0.5 * (rL + rV), 0.5 * (rL + rV)))
+    o, s = make_pair(w, rho=rho)
+    o.run(20)
+    s.step(20)
+    compare(o, s, w, FP64_BAR, f"degenerate {shape}")
+
+
+def test_fp32_form_vs_oracle():
+    """FP32 populations + FP64 EOS: densities within 1e-4 of the FP64 oracle."""
+    w = wl.WORKLOADS["binary_slab_2d"].scaled((64, 8))
+    announce("fp32 form 64x8")
+    o, s = make_pair(w, precision="fp32")
+    for k in (1, 999):
+        o.run(k)
+        s.step(k)
+        fo, fs = o.fields(), s.fields()
+        er = rel(fs["rho_molar"], fo["rho_molar"])
+        ep = rel(fs["p"], fo["p"])
+        print(f"  fp32 steps={o.steps}: rho {er:.2e} p {ep:.2e}", flush=True)
+        assert er < FP32_BAR and ep < FP32_BAR
+
+
+def test_fp32_form_3d_mrt():
+    w = wl.WORKLOADS["ternary_droplets_3d"].scaled((20, 12, 9))
+    w.geometry = "slab"
+    w.u0 = 0.0
+    rho, u = smooth_3d_field(w)
+    announce("fp32 form D3Q19 MRT ternary")
+    o, s = make_pair(w, precision="fp32", rho=rho, u=u)
+    o.run(20)
+    s.step(20)
+    er = rel(s.fields()["rho_molar"], o.fields()["rho_molar"])
+    print(f"  rho {er:.2e}", flush=True)
+    assert er < FP32_BAR
+
+
+# --------------------------------------------------------------- invariants
+def test_mass_conservation_and_determinism():
+    w = wl.WORKLOADS["binary_slab_2d"].scaled((64, 8))
+    announce("mass + determinism")
+    rho, u = wl.initial_field(w)
+    p = F.Params.from_workload(w)
+    a, b = F.Solver(p), F.Solver(p)
+    a.set_state(rho)
+    b.set_state(rho)
+    m0 = a.mass()
+    a.step(1000)
+    b.step(1000)
+    m1 = a.mass()
+    assert np.max(np.abs(m1 / m0 - 1)) < 1e-13
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_checkpoint_resume_bitwise():
+    w = wl.WORKLOADS["ternary_droplet_2d"].scaled((40, 32))
+    announce("checkpoint")
+    for prec in ("fp64", "fp32"):
+        rho, u = wl.initial_field(w)
+        p = F.Params.from_workload(w, precision=prec)
+        a = F.Solver(p)
+        a.set_state(rho)
+        a.step(100)
+        blob = a.get_state_raw()
+        a.step(50)
+        b = F.Solver(p)
+        b.set_state_raw(blob)
+        assert b.steps == 100
+        b.step(50)
+        assert np.array_equal(a.populations(), b.populations()), prec
+
+
+def test_domain_errors():
+    w = wl.WORKLOADS["binary_slab_2d"].scaled((16, 4))
+    announce("domain errors")
+    p = F.Params.from_workload(w)
+    s = F.Solver(p)
+    rho, _ = wl.initial_field(w)
+    bad = rho.copy()
+    bad[0, 0, 0, 3] = -1.0
+    with pytest.raises(F.FLError) as ei:
+        s.set_state(bad)
+    assert ei.value.status == F.FL_EDOMAIN
+    bad = rho.copy()
+    bad[1, 0, 0, 5] = np.nan
+    with pytest.raises(F.FLError):
+        s.set_state(bad)
+    dense = rho.copy() * 3.0        # rho~ b_m >= 1
+    with pytest.raises(F.FLError):
+        s.set_state(dense)
+    s.set_state(rho)
+    s.step(5)
+
+
+def test_numeric_failure_is_reported():
+    """A white-noise 3-D ternary field goes unstable (the D3Q19 well-balanced
+    scheme's high-wavenumber modes grow); the step reports FL_ENUMERIC."""
+    w = wl.WORKLOADS["ternary_droplets_3d"].scaled((24, 16, 16))
+    w.noise = 0.05
+    announce("numeric failure")
+    p = F.Params.from_workload(w, precision="fp64")
+    s = F.Solver(p)
+    rho, u = wl.initial_field(w)
+    s.set_state(rho, u)
+    with pytest.raises(F.FLError) as ei:
+        s.step(400)
+    assert ei.value.status == F.FL_ENUMERIC
+
+
+def test_run_until_residual():
+    w = wl.WORKLOADS["binary_slab_2d"].scaled((32, 2))
+    w.noise = 0.0
+    announce("run_until")
+    p = F.Params.from_workload(w)
+    s = F.Solver(p)
+    rho, _ = wl.initial_field(w)
+    s.set_state(rho)
+    conv, done, res = s.run_until(1e-8, 500, 40000)
+    print(f"  converged={conv} steps={done} residual={res:.2e}", flush=True)
+    assert conv and res < 1e-8 and done % 500 == 0
