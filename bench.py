@@ -58,10 +58,10 @@ def algorithmic_bytes(w, precision):
     ref = 0 if precision == "fp64" else 4 * nc
     pops = Q * nc * s
     k1 = pops + ref + 2 * 8 * nc
-    k2 = 2 * pops + ref + 2 * 8 * nc + 2 * 8 * D
-    # SURVEY per-node-step figure: populations once in and out, FP64 aux once
-    # each way, force history once each way
-    step = 2 * pops + 32 * nc + 16 * D
+    k2 = 2 * pops + ref + 2 * 8 * nc + 2 * s * D
+    # per-node-step figure: populations once in and out, the FP64 densities and
+    # ln f once each way, the force history (population precision) once each way
+    step = 2 * pops + 32 * nc + 2 * s * D
     return {"k_moments_eos": k1, "k_collide_stream": k2, "step": step}
 
 
@@ -151,10 +151,16 @@ def main():
         n = 1 << 28  # 1 GiB of float32
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(3):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 x {4 * n} bytes read + written", file=sys.stderr, flush=True)
+        gbps = 3 * 2 * 4 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(f"[bench] copy calibration: 4 x {4 * n} bytes read + written; "
+              f"copy bandwidth {gbps:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
         del a, b
 
     solver.step(args.warmup)

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -32,7 +33,7 @@ struct fl_solver {
     int cur = 0;
     double* rt = nullptr;
     double* lnf = nullptr;
-    double* fsum = nullptr;
+    void* fsum = nullptr;                  // force history, population precision
     float* rref = nullptr;
     double* snap = nullptr;
     double* out = nullptr;                 // (D + 1) * N scratch for field export
@@ -93,7 +94,7 @@ Layout layout_for(const fl_params* p) {
     L.pop = take(2 * nc * Q * N * es);
     L.rt = take(nc * N * 8);
     L.lnf = take(nc * N * 8);
-    L.fsum = take((size_t)D * N * 8);
+    L.fsum = take((size_t)D * N * es);
     L.rref = take(p->precision == FL_FP64 ? 0 : nc * N * 4);
     L.snap = take(nc * N * 8);
     L.out = take((size_t)(D + 1) * N * 8);
@@ -189,6 +190,17 @@ int setup(fl_solver* s, const fl_params* p) {
     s->lc.nc = p->ncomp;
     s->lc.precision = p->precision;
     s->lc.mrt = p->collision == FL_MRT;
+    // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0"
+    if (const char* t = std::getenv("FUGLBM_TUNE")) {
+        int v;
+        const char* q;
+        if ((q = std::strstr(t, "k1block=")) && std::sscanf(q + 8, "%d", &v) == 1 && v >= 64 && v <= 256 && v % 64 == 0)
+            s->lc.block_k1 = v;
+        if ((q = std::strstr(t, "k2block=")) && std::sscanf(q + 8, "%d", &v) == 1 && v >= 64 && v <= 256 && v % 64 == 0)
+            s->lc.block_k2 = v;
+        if ((q = std::strstr(t, "remap=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.xcd_remap = v != 0;
+        if ((q = std::strstr(t, "nt=")) && std::sscanf(q + 3, "%d", &v) == 1) s->lc.nt_store = v != 0;
+    }
     return FL_OK;
 }
 
@@ -200,7 +212,7 @@ int carve(fl_solver* s, void* base) {
     s->pop[1] = b + L.pop + half;
     s->rt = (double*)(b + L.rt);
     s->lnf = (double*)(b + L.lnf);
-    s->fsum = (double*)(b + L.fsum);
+    s->fsum = (void*)(b + L.fsum);
     s->rref = s->prm.precision == FL_FP64 ? nullptr : (float*)(b + L.rref);
     s->snap = (double*)(b + L.snap);
     s->out = (double*)(b + L.out);
@@ -211,7 +223,7 @@ int carve(fl_solver* s, void* base) {
     HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
     HIP_TRY(s, hipMemsetAsync(s->err, 0, 256, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->pop[0], 0, 2 * half, s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->fsum, 0, (size_t)s->D * s->N * 8, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->fsum, 0, (size_t)s->D * s->N * s->pop_elem, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return FL_OK;
 }
@@ -523,7 +535,7 @@ int fl_run_until(fl_solver* s, double tol, long check_every, long max_steps, lon
 
 int fl_state_bytes(const fl_solver* s, size_t* bytes) {
     if (!s || !bytes) return FL_EINVAL;
-    *bytes = 16 + s->nc * s->Q * s->N * s->pop_elem + s->D * s->N * 8 + (s->rref ? s->nc * s->N * 4 : 0);
+    *bytes = 16 + s->nc * s->Q * s->N * s->pop_elem + s->D * s->N * s->pop_elem + (s->rref ? s->nc * s->N * 4 : 0);
     return FL_OK;
 }
 
@@ -537,8 +549,8 @@ int fl_get_state_raw(fl_solver* s, void* host_buf, size_t bytes) {
     const size_t pb = s->nc * s->Q * s->N * s->pop_elem;
     HIP_TRY(s, hipMemcpyAsync(b + off, s->pop[s->cur], pb, hipMemcpyDeviceToHost, s->stream));
     off += pb;
-    HIP_TRY(s, hipMemcpyAsync(b + off, s->fsum, s->D * s->N * 8, hipMemcpyDeviceToHost, s->stream));
-    off += s->D * s->N * 8;
+    HIP_TRY(s, hipMemcpyAsync(b + off, s->fsum, s->D * s->N * s->pop_elem, hipMemcpyDeviceToHost, s->stream));
+    off += s->D * s->N * s->pop_elem;
     if (s->rref) HIP_TRY(s, hipMemcpyAsync(b + off, s->rref, s->nc * s->N * 4, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return FL_OK;
@@ -556,8 +568,8 @@ int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
     s->cur = 0;
     HIP_TRY(s, hipMemcpyAsync(s->pop[0], b + off, pb, hipMemcpyHostToDevice, s->stream));
     off += pb;
-    HIP_TRY(s, hipMemcpyAsync(s->fsum, b + off, s->D * s->N * 8, hipMemcpyHostToDevice, s->stream));
-    off += s->D * s->N * 8;
+    HIP_TRY(s, hipMemcpyAsync(s->fsum, b + off, s->D * s->N * s->pop_elem, hipMemcpyHostToDevice, s->stream));
+    off += s->D * s->N * s->pop_elem;
     if (s->rref) HIP_TRY(s, hipMemcpyAsync(s->rref, b + off, s->nc * s->N * 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->steps = hdr[0];

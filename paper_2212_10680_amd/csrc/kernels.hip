@@ -4,7 +4,7 @@
 //   populations  g[c][a][n]   (P = double, or float in the FP32 form where the
 //                             rest slot a = 0 holds g_0 minus rref[c][n])
 //   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64)
-//   fsum[k][n]                sum_i F_i of the previous step (FP64)
+//   fsum[k][n]                sum_i F_i of the previous step (population precision)
 //   rref[c][n]                rest-population reference (FP32 form only)
 //
 // Step = k_moments_eos (steps 1-5: reads every population once, writes rt and
@@ -45,14 +45,32 @@ __device__ __forceinline__ int wrapi(int v, int m) {
     return v < 0 ? v + m : v;
 }
 
+// Node of this thread.  With xcd_chunk > 0 the hardware block b (dispatched
+// round-robin over the 8 XCDs) handles logical block (b % 8) * xcd_chunk + b / 8,
+// so every XCD sweeps one contiguous range of nodes and its L2 keeps the
+// neighbouring planes the stencil needs.
+__device__ __forceinline__ int node_index(int xcd_chunk) {
+    const int b = blockIdx.x;
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    return lb * blockDim.x + threadIdx.x;
+}
+
+template <typename P>
+__device__ __forceinline__ void store_pop(P* p, P v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // ----------------------------------------------------------------- step 1-5
 template <int LAT, int NC, typename P>
 __global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __restrict__ g,
                                                      const float* __restrict__ rref,
                                                      double* __restrict__ rt, double* __restrict__ lnf,
-                                                     int* __restrict__ err) {
+                                                     int* __restrict__ err, int xcd_chunk) {
     using L = Lat<LAT>;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = node_index(xcd_chunk);
     if (n >= kp.N) return;
     const size_t N = kp.N;
     P gv[NC][L::Q];
@@ -77,11 +95,11 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
                                                         const float* __restrict__ rref,
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
-                                                        double* __restrict__ fsum) {
+                                                        P* __restrict__ fsum, int xcd_chunk, int nt) {
     using L = Lat<LAT>;
     constexpr int D = L::D, Q = L::Q;
     using T = P;  // collision precision
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = node_index(xcd_chunk);
     if (n >= kp.N) return;
     const size_t N = kp.N;
     const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
@@ -187,7 +205,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : fsum[(size_t)k * N + n];
+        const double fk = kp.force_level ? Fs[k] : (double)fsum[(size_t)k * N + n];
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
 
@@ -203,10 +221,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
         collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
-            gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])] = out[a];
+            store_pop(&gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])], out[a], nt != 0);
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = Fs[k];
+    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = (P)Fs[k];
 }
 
 // ------------------------------------------------------------ initial state
@@ -214,7 +232,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
 template <int LAT, int NC, typename P>
 __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restrict__ rho_molar,
                                               const double* __restrict__ uin, P* __restrict__ g,
-                                              float* __restrict__ rref, double* __restrict__ fsum) {
+                                              float* __restrict__ rref, P* __restrict__ fsum) {
     using L = Lat<LAT>;
     constexpr int D = L::D, Q = L::Q;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,14 +261,14 @@ __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restri
         }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = 0.0;
+    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = (P)0;
 }
 
 // ------------------------------------------------------------ output fields
 template <int LAT, int NC, typename P>
 __global__ __launch_bounds__(256) void k_fields(KParams kp, const P* __restrict__ g,
                                                 const float* __restrict__ rref,
-                                                const double* __restrict__ fsum,
+                                                const P* __restrict__ fsum,
                                                 double* __restrict__ rho_molar, double* __restrict__ uout,
                                                 double* __restrict__ pout, double* __restrict__ lnf) {
     using L = Lat<LAT>;
@@ -276,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fields(KParams kp, const P* __restrict_
         }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) uout[(size_t)k * N + n] = (j[k] + 0.5 * fsum[(size_t)k * N + n]) / rtot;
+    for (int k = 0; k < D; ++k) uout[(size_t)k * N + n] = (j[k] + 0.5 * (double)fsum[(size_t)k * N + n]) / rtot;
     double p;
     eos_lnf<NC>(kp, r, lf, &p);
     pout[n] = p;
@@ -424,44 +442,58 @@ void dispatch(int lattice, int nc, int precision, F&& f) {
     constexpr int NC = decltype(ncc)::value;      \
     using P = typename decltype(pt)::type
 
+static inline int xcd_chunk_for(const LaunchCfg& lc, int nblocks) {
+    return lc.xcd_remap ? (nblocks + 7) / 8 : 0;
+}
+
+static inline dim3 grid_remapped(int nblocks, int chunk) { return dim3(chunk > 0 ? 8 * chunk : nblocks); }
+
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* rt, double* lnf, int* err) {
+    const int bs = lc.block_k1;
+    const int nb = (kp.N + bs - 1) / bs;
+    const int ch = xcd_chunk_for(lc, nb);
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
-        k_moments_eos<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
-            kp, (const P*)g, rref, rt, lnf, err);
+        k_moments_eos<LAT, NC, P><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
+            kp, (const P*)g, rref, rt, lnf, err, ch);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
-                                 const float* rref, const double* rt, const double* lnf, double* fsum) {
+                                 const float* rref, const double* rt, const double* lnf, void* fsum) {
+    const int bs = lc.block_k2;
+    const int nb = (kp.N + bs - 1) / bs;
+    const int ch = xcd_chunk_for(lc, nb);
+    const int nt = lc.nt_store ? 1 : 0;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         if (lc.mrt)
-            k_collide_stream<LAT, NC, P, true><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, fsum);
+            k_collide_stream<LAT, NC, P, true><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (P*)fsum, ch, nt);
         else
-            k_collide_stream<LAT, NC, P, false><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, fsum);
+            k_collide_stream<LAT, NC, P, false><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (P*)fsum, ch, nt);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
-                       void* g, float* rref, double* fsum) {
+                       void* g, float* rref, void* fsum) {
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
-        k_init<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, rho_molar, u, (P*)g, rref, fsum);
+        k_init<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, rho_molar, u, (P*)g, rref,
+                                                                        (P*)fsum);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
-                         const double* fsum, double* rho_molar, double* u, double* p, double* lnf) {
+                         const void* fsum, double* rho_molar, double* u, double* p, double* lnf) {
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
-        k_fields<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, (const P*)g, rref, fsum,
+        k_fields<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, (const P*)g, rref, (const P*)fsum,
                                                                           rho_molar, u, p, lnf);
     });
     return hipGetLastError();

@@ -13,16 +13,21 @@ struct LaunchCfg {
     int precision;  // 0 FP64, 1 FP32 populations
     bool mrt;
     hipStream_t stream;
+    int block_k1 = 256;     // threads per block of the moments/EOS kernel
+    int block_k2 = 64;      // threads per block of the collide/stream kernel
+    bool xcd_remap = true;  // XCD-contiguous block order
+    bool nt_store = false;  // non-temporal population stores
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* rt, double* lnf, int* err);
+// fsum: force history, in the population precision
 hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
-                                 const float* rref, const double* rt, const double* lnf, double* fsum);
+                                 const float* rref, const double* rt, const double* lnf, void* fsum);
 hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
-                       void* g, float* rref, double* fsum);
+                       void* g, float* rref, void* fsum);
 hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
-                         const double* fsum, double* rho_molar, double* u, double* p, double* lnf);
+                         const void* fsum, double* rho_molar, double* u, double* p, double* lnf);
 hipError_t launch_export_pops(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* out);
 // Deterministic reduction: out[0..nc) = sum_x rho_i, out[nc..2nc) = max |rho_i - snap_i|
