@@ -114,6 +114,64 @@ def cpu_baseline(w, budget_s=15.0):
                       f"FP64, {w.collision}, {dt:.1f} s"}
 
 
+def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, plain_subset=16,
+                  tol=1e-10, check_every=1000):
+    """Batched VLE serving: FP32-population server vs the plain FP64 path.
+
+    Requests: binary D2Q9 L x 8 slabs, L log-uniform in [64, 2048], feed z1
+    redrawn until a S_V = 0.5 state exists; each runs until the rate residual is
+    below tol (checked every check_every steps) or max_steps.  Closed loop first
+    (all requests present at t = 0) for the saturation throughput, then a
+    seeded Poisson stream at 0.8 of it, admitted by the pool budget.
+    """
+    from paper_2212_10680_amd import serving
+
+    w = wl.WORKLOADS["serving_binary_2d"]
+    p32 = F.Params.from_workload(w, precision="fp32")
+    reqs, rejected = wl.serving_requests(n=n_requests, seed=0)
+    srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
+    closed = serving.serve(srv, reqs, np.zeros(len(reqs)), tol, check_every, max_steps, tick_ms)
+    srv.close()
+    print(f"[bench] serving closed loop: {closed['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+    rate = 0.8 * closed["solves_per_s"]
+    arrivals = serving.poisson_arrivals(len(reqs), rate, seed=0)
+    srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
+    batched = {}
+    opened = serving.serve(srv, reqs, arrivals, tol, check_every, max_steps, tick_ms,
+                           on_result=lambda rec, rho: batched.__setitem__(rec["i"], (rho, rec["steps"])))
+    srv.close()
+    print(f"[bench] serving open loop: {opened['solves_per_s']:.1f} solves/s, "
+          f"p99 {opened['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
+    # plain FP64 path (one request at a time, two kernels per step) on a subset
+    idx = list(range(0, len(reqs), max(1, len(reqs) // plain_subset)))[:plain_subset]
+    p64 = F.Params.from_workload(w, precision="fp64")
+    times, diffs, psteps = [], [], []
+    for i in idx:
+        rho, steps, res, conv, dt = serving.solve_plain(p64, reqs[i], tol, check_every, max_steps)
+        times.append(dt)
+        psteps.append(steps)
+        if i in batched:
+            # accuracy of the FP32 server against FP64 at the same step count
+            b, bsteps = batched[i]
+            if bsteps != steps:
+                rho = serving.solve_plain(p64, reqs[i], 0.0, check_every, bsteps)[0]
+            diffs.append(float(np.max(np.abs(b.reshape(rho.shape) - rho)) / np.max(np.abs(rho))))
+    plain_rate = len(idx) / sum(times)
+    strip = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items() if k != "records"}
+    return {
+        "requests": len(reqs), "rejected_feed_draws": rejected, "tol": tol, "check_every": check_every,
+        "max_steps": max_steps, "pool_MB": pool_mb, "tick_ms": tick_ms, "precision": "fp32 populations",
+        "closed_loop": strip(closed),
+        "open_loop": dict(strip(opened), arrival_rate_per_s=round(rate, 3)),
+        "plain_fp64": {"subset": len(idx), "solves_per_s": round(plain_rate, 3),
+                       "p50_service_s": round(float(np.percentile(times, 50)), 4),
+                       "p99_service_s": round(float(np.percentile(times, 99)), 4),
+                       "mean_steps": float(np.mean(psteps))},
+        "speedup_vs_plain_fp64": round(opened["solves_per_s"] / plain_rate, 2),
+        "max_rel_diff_fp32_batched_vs_fp64_plain": max(diffs) if diffs else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +180,9 @@ def main():
     ap.add_argument("--workload", default="binary_slab_3d", choices=sorted(wl.WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched serving leg")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-max-steps", type=int, default=50000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (PMC byte-counter scale)")
     args = ap.parse_args()
@@ -214,6 +275,8 @@ def main():
         "roofline": roofline,
         "mass_total": [float(m) for m in mass],
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -176,6 +176,62 @@ int fl_state_bytes(const fl_solver* s, size_t* bytes);
 int fl_get_state_raw(fl_solver* s, void* host_buf, size_t bytes);
 int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes);
 
+
+/* ------------------------------------------------------------------------
+ * Batched server: many independent lattices (requests) with the same
+ * components, temperature and numerics, each advanced by the same update.
+ * Continuous batching at the granularity of a tick: fl_server_tick advances
+ * every admitted, unfinished request in ONE batched kernel launch (one
+ * workgroup per request, up to `steps` steps each, each request checking its
+ * own residual every check_every of its own steps, as in fl_run_until).
+ * Requests are admitted and retired between ticks, as slots and pool memory
+ * free up.  A request's arithmetic depends only on its own state and step
+ * count, so its result is the same alone and in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct fl_server fl_server;
+
+/* base: components, kij, T, R, eos, lattice, collision, tau, mrt_rates,
+ * precision, force_time_level (nx, ny, nz are ignored: they come with each
+ * request).  pool_bytes: device memory reserved for request state; admission
+ * fails with FL_EAGAIN when a request does not fit.  max_slots: most requests
+ * in flight.  hip_stream: stream for all server work (NULL: own stream). */
+int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, void* hip_stream,
+                     fl_server** out);
+void fl_server_destroy(fl_server* srv);
+const char* fl_server_last_error(const fl_server* srv);
+
+/* Pool bytes one request of nx*ny*nz nodes occupies. */
+int fl_server_request_bytes(const fl_server* srv, int nx, int ny, int nz, size_t* bytes);
+
+/* Admit a request: molar densities rho_molar [ncomp][nx*ny*nz] (host), run
+ * until the residual of fl_run_until is below tol (checked every check_every
+ * steps) or max_steps.  *id receives the request id.  FL_EAGAIN when no slot
+ * or pool memory is free now, FL_EDOMAIN for an invalid initial state,
+ * FL_EINVAL for bad sizes. */
+int fl_server_submit(fl_server* srv, int nx, int ny, int nz, const double* rho_molar, double tol,
+                     long check_every, long max_steps, uint64_t* id);
+
+/* One tick (synchronous): every running request advances by up to `steps`
+ * steps, and stops early once max_ms milliseconds of device time have passed
+ * since its workgroup started (max_ms <= 0: no time limit), so that large and
+ * small requests leave the tick together.  *active receives the requests still
+ * running. */
+int fl_server_tick(fl_server* srv, long steps, double max_ms, int* active);
+
+/* Ids of finished, not yet collected requests (up to cap); *n the count. */
+int fl_server_poll(fl_server* srv, uint64_t* ids, int cap, int* n);
+
+/* Collect a finished request: molar densities [ncomp][N] (may be NULL), steps
+ * run, last residual, and its status (FL_OK converged, FL_ENOTCONV max_steps
+ * reached, FL_ENUMERIC left the EOS domain).  Frees its slot and memory.
+ * FL_EAGAIN if the request is still running, FL_EINVAL for an unknown id. */
+int fl_server_result(fl_server* srv, uint64_t id, double* rho_molar, long* steps, double* residual,
+                     int* status);
+
+/* Occupancy: requests in flight, free slots, pool bytes in use and total. */
+int fl_server_info(const fl_server* srv, int* active, int* free_slots, size_t* pool_used,
+                   size_t* pool_total);
+
 #ifdef __cplusplus
 }
 #endif

@@ -200,6 +200,8 @@ int setup(fl_solver* s, const fl_params* p) {
             s->lc.block_k2 = v;
         if ((q = std::strstr(t, "remap=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.xcd_remap = v != 0;
         if ((q = std::strstr(t, "nt=")) && std::sscanf(q + 3, "%d", &v) == 1) s->lc.nt_store = v != 0;
+        if ((q = std::strstr(t, "serve=")) && std::sscanf(q + 6, "%d", &v) == 1 && (v == 256 || v == 512 || v == 1024))
+            s->lc.serve_block = v;
     }
     return FL_OK;
 }
@@ -574,6 +576,311 @@ int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->steps = hdr[0];
     s->snap_valid = false;
+    return FL_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== server
+#include <map>
+
+struct fl_server {
+    fl_solver cfg;                       // parameters, constants and launch config only
+    char* pool = nullptr;
+    size_t pool_bytes = 0;
+    std::map<size_t, size_t> free_list;  // offset -> size (first fit, merged on free)
+    int max_slots = 0;
+    struct Req {
+        uint64_t id;
+        fl::SlotDesc d;
+        size_t off, bytes;
+    };
+    std::vector<Req> reqs;               // running or finished-not-collected
+    fl::SlotDesc* d_descs = nullptr;
+    fl::SlotDesc* h_descs = nullptr;
+    uint64_t next_id = 1;
+    int wall_khz = 0;
+    bool own_stream = false;
+    std::string last_error;
+};
+
+namespace {
+
+int sfail(fl_server* s, int code, const std::string& msg) {
+    if (s) s->last_error = msg;
+    return code;
+}
+
+#define SRV_TRY(s, expr)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) return sfail((s), FL_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+struct ReqLayout {
+    size_t pop0, pop1, rt, lnf, fsum, rref, snap, total;
+};
+
+ReqLayout req_layout(const fl_solver& c, size_t N) {
+    ReqLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off += align256(b); return o; };
+    const size_t pb = (size_t)c.nc * c.Q * N * c.pop_elem;
+    L.pop0 = take(pb);
+    L.pop1 = take(pb);
+    L.rt = take((size_t)c.nc * N * 8);
+    L.lnf = take((size_t)c.nc * N * 8);
+    L.fsum = take((size_t)c.D * N * c.pop_elem);
+    L.rref = take(c.prm.precision == FL_FP64 ? 0 : (size_t)c.nc * N * 4);
+    L.snap = take((size_t)c.nc * N * 8);
+    L.total = off;
+    return L;
+}
+
+bool pool_alloc(fl_server* s, size_t bytes, size_t* off) {
+    for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t roff = it->first + bytes;
+            s->free_list.erase(it);
+            if (rest) s->free_list[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(fl_server* s, size_t off, size_t bytes) {
+    auto it = s->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != s->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        s->free_list.erase(nx);
+    }
+    if (it != s->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            s->free_list.erase(it);
+        }
+    }
+}
+
+fl::KParams req_kparams(const fl_server* s, int nx, int ny, int nz) {
+    fl::KParams kp = s->cfg.kp;
+    kp.nx = nx;
+    kp.ny = ny;
+    kp.nz = nz;
+    kp.N = nx * ny * nz;
+    return kp;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, void* hip_stream, fl_server** out) {
+    if (!out) return FL_EINVAL;
+    *out = nullptr;
+    if (!base || max_slots < 1 || max_slots > 65535 || pool_bytes < 4096) return FL_EINVAL;
+    fl_params p = *base;
+    p.nx = p.ny = p.nz = 1;
+    const int v = fl_validate(&p);
+    if (v != FL_OK) return v;
+    fl_server* s = new (std::nothrow) fl_server();
+    if (!s) return FL_ENOMEM;
+    setup(&s->cfg, &p);
+    s->max_slots = max_slots;
+    s->pool_bytes = pool_bytes & ~size_t(255);
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        s->cfg.stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&s->cfg.stream, hipStreamNonBlocking);
+        s->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&s->pool, s->pool_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_descs, sizeof(fl::SlotDesc) * max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_descs, sizeof(fl::SlotDesc) * max_slots, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fl_server_destroy(s);
+        return FL_ENOMEM;
+    }
+    s->free_list[0] = s->pool_bytes;
+    *out = s;
+    return FL_OK;
+}
+
+void fl_server_destroy(fl_server* s) {
+    if (!s) return;
+    if (s->cfg.stream) (void)hipStreamSynchronize(s->cfg.stream);
+    if (s->pool) (void)hipFree(s->pool);
+    if (s->d_descs) (void)hipFree(s->d_descs);
+    if (s->h_descs) (void)hipHostFree(s->h_descs);
+    if (s->own_stream && s->cfg.stream) (void)hipStreamDestroy(s->cfg.stream);
+    delete s;
+}
+
+const char* fl_server_last_error(const fl_server* s) { return s ? s->last_error.c_str() : "null server"; }
+
+int fl_server_request_bytes(const fl_server* s, int nx, int ny, int nz, size_t* bytes) {
+    if (!s || !bytes || nx < 1 || ny < 1 || nz < 1) return FL_EINVAL;
+    if (s->cfg.D == 2 && nz != 1) return FL_EINVAL;
+    *bytes = req_layout(s->cfg, (size_t)nx * ny * nz).total;
+    return FL_OK;
+}
+
+int fl_server_submit(fl_server* s, int nx, int ny, int nz, const double* rho_molar, double tol, long check_every,
+                     long max_steps, uint64_t* id) {
+    if (!s || !rho_molar || !id || check_every < 1 || max_steps < 0 || !(tol >= 0.0)) return FL_EINVAL;
+    size_t bytes;
+    if (fl_server_request_bytes(s, nx, ny, nz, &bytes) != FL_OK) return FL_EINVAL;
+    const size_t N = (size_t)nx * ny * nz;
+    if (N >= (size_t)1 << 30) return FL_EINVAL;
+    const int nc = s->cfg.nc;
+    std::vector<double> node(nc);
+    for (size_t n = 0; n < N; ++n) {
+        for (int c = 0; c < nc; ++c) node[c] = rho_molar[(size_t)c * N + n];
+        if (!host_in_domain(s->cfg.kp, nc, node.data()))
+            return sfail(s, FL_EDOMAIN, "initial state outside the EOS domain at node " + std::to_string(n));
+    }
+    if ((int)s->reqs.size() >= s->max_slots) return sfail(s, FL_EAGAIN, "no free slot");
+    size_t off;
+    if (!pool_alloc(s, bytes, &off)) return sfail(s, FL_EAGAIN, "pool memory exhausted");
+    const ReqLayout L = req_layout(s->cfg, N);
+    const fl::KParams kp = req_kparams(s, nx, ny, nz);
+    fl::LaunchCfg lc = s->cfg.lc;
+    lc.stream = s->cfg.stream;
+    char* b = s->pool + off;
+    hipError_t e = hipMemcpyAsync(b + L.rt, rho_molar, sizeof(double) * nc * N, hipMemcpyHostToDevice, lc.stream);
+    float* rref = s->cfg.prm.precision == FL_FP64 ? nullptr : (float*)(b + L.rref);
+    if (e == hipSuccess) e = fl::launch_init(lc, kp, (const double*)(b + L.rt), nullptr, b + L.pop0, rref, b + L.fsum);
+    if (e == hipSuccess) e = fl::launch_snapshot(lc, kp, b + L.pop0, rref, (double*)(b + L.snap));
+    if (e == hipSuccess) e = hipStreamSynchronize(lc.stream);
+    if (e != hipSuccess) {
+        pool_free(s, off, bytes);
+        return sfail(s, FL_EDEVICE, std::string("submit: ") + hipGetErrorString(e));
+    }
+    fl_server::Req r;
+    r.id = s->next_id++;
+    r.off = off;
+    r.bytes = bytes;
+    std::memset(&r.d, 0, sizeof(r.d));
+    r.d.nx = nx;
+    r.d.ny = ny;
+    r.d.nz = nz;
+    r.d.N = (int)N;
+    r.d.off_pop[0] = (long long)(off + L.pop0);
+    r.d.off_pop[1] = (long long)(off + L.pop1);
+    r.d.off_rt = (long long)(off + L.rt);
+    r.d.off_lnf = (long long)(off + L.lnf);
+    r.d.off_fsum = (long long)(off + L.fsum);
+    r.d.off_rref = (long long)(off + L.rref);
+    r.d.off_snap = (long long)(off + L.snap);
+    r.d.max_steps = max_steps;
+    r.d.check_every = check_every;
+    r.d.tol = tol;
+    r.d.residual = INFINITY;
+    r.d.cur = 0;
+    r.d.status = fl::kSlotRunning;
+    s->reqs.push_back(r);
+    *id = r.id;
+    return FL_OK;
+}
+
+int fl_server_tick(fl_server* s, long steps, double max_ms, int* active) {
+    if (!s || steps < 0) return FL_EINVAL;
+    long long budget = 0;
+    if (max_ms > 0.0) {
+        if (s->wall_khz == 0) {
+            int dev = 0, khz = 0;
+            SRV_TRY(s, hipGetDevice(&dev));
+            SRV_TRY(s, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            s->wall_khz = khz > 0 ? khz : 100000;
+        }
+        budget = (long long)(max_ms * s->wall_khz);
+        if (budget < 1) budget = 1;
+    }
+    std::vector<int> run;
+    for (int k = 0; k < (int)s->reqs.size(); ++k)
+        if (s->reqs[k].d.status == fl::kSlotRunning) run.push_back(k);
+    const int n = (int)run.size();
+    if (n > 0 && steps > 0) {
+        for (int i = 0; i < n; ++i) s->h_descs[i] = s->reqs[run[i]].d;
+        fl::LaunchCfg lc = s->cfg.lc;
+        lc.stream = s->cfg.stream;
+        SRV_TRY(s, hipMemcpyAsync(s->d_descs, s->h_descs, sizeof(fl::SlotDesc) * n, hipMemcpyHostToDevice, lc.stream));
+        SRV_TRY(s, fl::launch_serve_tick(lc, s->cfg.kp, s->pool, s->d_descs, n, steps, budget));
+        SRV_TRY(s, hipMemcpyAsync(s->h_descs, s->d_descs, sizeof(fl::SlotDesc) * n, hipMemcpyDeviceToHost, lc.stream));
+        SRV_TRY(s, hipStreamSynchronize(lc.stream));
+        for (int i = 0; i < n; ++i) s->reqs[run[i]].d = s->h_descs[i];
+    }
+    if (active) {
+        int a = 0;
+        for (auto& r : s->reqs) a += r.d.status == fl::kSlotRunning;
+        *active = a;
+    }
+    return FL_OK;
+}
+
+int fl_server_poll(fl_server* s, uint64_t* ids, int cap, int* n) {
+    if (!s || !n || (cap > 0 && !ids)) return FL_EINVAL;
+    int k = 0;
+    for (auto& r : s->reqs)
+        if (r.d.status != fl::kSlotRunning && k < cap) ids[k++] = r.id;
+    *n = k;
+    return FL_OK;
+}
+
+int fl_server_result(fl_server* s, uint64_t id, double* rho_molar, long* steps, double* residual, int* status) {
+    if (!s) return FL_EINVAL;
+    int k = -1;
+    for (int i = 0; i < (int)s->reqs.size(); ++i)
+        if (s->reqs[i].id == id) k = i;
+    if (k < 0) return sfail(s, FL_EINVAL, "unknown request id");
+    fl_server::Req r = s->reqs[k];
+    if (r.d.status == fl::kSlotRunning) return FL_EAGAIN;
+    if (rho_molar) {
+        const fl::KParams kp = req_kparams(s, r.d.nx, r.d.ny, r.d.nz);
+        fl::LaunchCfg lc = s->cfg.lc;
+        lc.stream = s->cfg.stream;
+        const size_t N = r.d.N;
+        double* tmp = nullptr;
+        SRV_TRY(s, hipMallocAsync((void**)&tmp, sizeof(double) * (s->cfg.D + 1) * N, lc.stream));
+        const float* rref = s->cfg.prm.precision == FL_FP64 ? nullptr : (const float*)(s->pool + r.d.off_rref);
+        hipError_t e = fl::launch_fields(lc, kp, s->pool + r.d.off_pop[r.d.cur], rref, s->pool + r.d.off_fsum,
+                                         (double*)(s->pool + r.d.off_rt), tmp, tmp + (size_t)s->cfg.D * N,
+                                         (double*)(s->pool + r.d.off_lnf));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rho_molar, s->pool + r.d.off_rt, sizeof(double) * s->cfg.nc * N, hipMemcpyDeviceToHost,
+                               lc.stream);
+        (void)hipFreeAsync(tmp, lc.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(lc.stream);
+        if (e != hipSuccess) return sfail(s, FL_EDEVICE, std::string("result: ") + hipGetErrorString(e));
+    }
+    if (steps) *steps = (long)r.d.steps;
+    if (residual) *residual = r.d.residual;
+    if (status)
+        *status = r.d.status == fl::kSlotConverged ? FL_OK : r.d.status == fl::kSlotMaxSteps ? FL_ENOTCONV : FL_ENUMERIC;
+    pool_free(s, r.off, r.bytes);
+    s->reqs.erase(s->reqs.begin() + k);
+    return FL_OK;
+}
+
+int fl_server_info(const fl_server* s, int* active, int* free_slots, size_t* pool_used, size_t* pool_total) {
+    if (!s) return FL_EINVAL;
+    int a = 0;
+    size_t used = 0;
+    for (auto& r : s->reqs) {
+        a += r.d.status == fl::kSlotRunning;
+        used += r.bytes;
+    }
+    if (active) *active = a;
+    if (free_slots) *free_slots = s->max_slots - (int)s->reqs.size();
+    if (pool_used) *pool_used = used;
+    if (pool_total) *pool_total = s->pool_bytes;
     return FL_OK;
 }
 

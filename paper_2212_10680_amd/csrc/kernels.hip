@@ -63,16 +63,18 @@ __device__ __forceinline__ void store_pop(P* p, P v, bool nt) {
         *p = v;
 }
 
+// Lattice extent (per solver, or per request in the batched server).
+struct Dims {
+    int nx, ny, nz, N;
+};
+
 // ----------------------------------------------------------------- step 1-5
+// Steps 1-5 at node n: densities, molar densities, mixing, EOS, ln f.
 template <int LAT, int NC, typename P>
-__global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __restrict__ g,
-                                                     const float* __restrict__ rref,
-                                                     double* __restrict__ rt, double* __restrict__ lnf,
-                                                     int* __restrict__ err, int xcd_chunk) {
+__device__ __forceinline__ bool node_moments_eos(const KParams& kp, int n, size_t N, const P* __restrict__ g,
+                                                 const float* __restrict__ rref, double* __restrict__ rt,
+                                                 double* __restrict__ lnf) {
     using L = Lat<LAT>;
-    const int n = node_index(xcd_chunk);
-    if (n >= kp.N) return;
-    const size_t N = kp.N;
     P gv[NC][L::Q];
     load_pops<L, NC, P>(g, n, N, gv);
     double rho[NC], mov[NC], r[NC], lf[NC];
@@ -85,24 +87,34 @@ __global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __rest
     const bool ok = eos_lnf<NC>(kp, r, lf, nullptr);
 #pragma unroll
     for (int c = 0; c < NC; ++c) lnf[(size_t)c * N + n] = lf[c];
-    if (!ok) atomicOr(err, 1);
+    return ok;
+}
+
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __restrict__ g,
+                                                     const float* __restrict__ rref,
+                                                     double* __restrict__ rt, double* __restrict__ lnf,
+                                                     int* __restrict__ err, int xcd_chunk) {
+    const int n = node_index(xcd_chunk);
+    if (n >= kp.N) return;
+    if (!node_moments_eos<LAT, NC, P>(kp, n, kp.N, g, rref, rt, lnf)) atomicOr(err, 1);
 }
 
 // ---------------------------------------------------------------- step 6-9
+// Steps 6-9 (and step 1's velocity) at node n; pushes the collided
+// populations to n + e_a of gn.
 template <int LAT, int NC, typename P, bool MRT>
-__global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __restrict__ g,
-                                                        P* __restrict__ gn,
-                                                        const float* __restrict__ rref,
-                                                        const double* __restrict__ rt,
-                                                        const double* __restrict__ lnf,
-                                                        P* __restrict__ fsum, int xcd_chunk, int nt) {
+__device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dims& dm, int n,
+                                                    const P* __restrict__ g, P* __restrict__ gn,
+                                                    const float* __restrict__ rref,
+                                                    const double* __restrict__ rt,
+                                                    const double* __restrict__ lnf,
+                                                    P* __restrict__ fsum, bool nt) {
     using L = Lat<LAT>;
     constexpr int D = L::D, Q = L::Q;
     using T = P;  // collision precision
-    const int n = node_index(xcd_chunk);
-    if (n >= kp.N) return;
-    const size_t N = kp.N;
-    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const size_t N = dm.N;
+    const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
     const int x = n % nx;
     const int t = n / nx;
     const int y = t % ny;
@@ -221,10 +233,23 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
         collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
-            store_pop(&gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])], out[a], nt != 0);
+            store_pop(&gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])], out[a], nt);
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = (P)Fs[k];
+}
+
+template <int LAT, int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __restrict__ g,
+                                                        P* __restrict__ gn,
+                                                        const float* __restrict__ rref,
+                                                        const double* __restrict__ rt,
+                                                        const double* __restrict__ lnf,
+                                                        P* __restrict__ fsum, int xcd_chunk, int nt) {
+    const int n = node_index(xcd_chunk);
+    if (n >= kp.N) return;
+    const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
+    node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, g, gn, rref, rt, lnf, fsum, nt != 0);
 }
 
 // ------------------------------------------------------------ initial state
@@ -517,6 +542,179 @@ hipError_t launch_reduce(const LaunchCfg& lc, const KParams& kp, const void* g, 
         FL_TYPES;
         k_reduce_partials<LAT, NC, P><<<nb, kRedBlock, 0, lc.stream>>>(kp, (const P*)g, rref, snap, partial);
         k_reduce_final<NC><<<1, kRedBlock, 0, lc.stream>>>(partial, nb, out);
+    });
+    return hipGetLastError();
+}
+
+
+// Densities of the current populations into snap (residual baseline).
+template <int LAT, int NC, typename P>
+__global__ __launch_bounds__(256) void k_snapshot(KParams kp, const P* __restrict__ g, const float* __restrict__ rref,
+                                                  double* __restrict__ snap) {
+    using L = Lat<LAT>;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    P gv[NC][L::Q];
+    load_pops<L, NC, P>(g, n, kp.N, gv);
+    double rho[NC], mov[NC];
+    densities<L, NC, P>(gv, rref, n, kp.N, rho, mov);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) snap[(size_t)c * kp.N + n] = rho[c];
+}
+
+hipError_t launch_snapshot(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref, double* snap) {
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        k_snapshot<LAT, NC, P><<<grid_for(kp.N, 256), 256, 0, lc.stream>>>(kp, (const P*)g, rref, snap);
+    });
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batched server
+// One workgroup advances one request: the two phases of a step are separated
+// by workgroup barriers (phase B reads the densities and ln f that other
+// threads of the workgroup wrote in phase A), every thread owns the same nodes
+// in every step, and the residual check every check_every request steps is a
+// workgroup max-reduction.  Nothing depends on other requests or on where the
+// tick boundaries fall.
+template <int LAT, int NC, typename P, bool MRT, int kServeBlock>
+__global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __restrict__ pool,
+                                                            SlotDesc* __restrict__ descs,
+                                                            long long steps, long long clock_budget) {
+    using L = Lat<LAT>;
+    __shared__ SlotDesc sd;
+    __shared__ int s_bad;
+    __shared__ int s_go;
+    __shared__ unsigned long long s_t0;
+    __shared__ double s_red[2 * NC][kServeBlock / 64];
+    if (threadIdx.x == 0) {
+        sd = descs[blockIdx.x];
+        s_bad = 0;
+        s_t0 = wall_clock64();
+    }
+    __syncthreads();
+    if (sd.status != kSlotRunning) return;
+    const Dims dm{sd.nx, sd.ny, sd.nz, sd.N};
+    const size_t N = sd.N;
+    P* pops[2] = {(P*)(pool + sd.off_pop[0]), (P*)(pool + sd.off_pop[1])};
+    double* rt = (double*)(pool + sd.off_rt);
+    double* lnf = (double*)(pool + sd.off_lnf);
+    P* fsum = (P*)(pool + sd.off_fsum);
+    const float* rref = sizeof(P) == 4 ? (const float*)(pool + sd.off_rref) : nullptr;
+    double* snap = (double*)(pool + sd.off_snap);
+    int cur = sd.cur;
+    long long done = sd.steps;
+    int status = kSlotRunning;
+    double residual = sd.residual;
+    for (long long s = 0; s < steps; ++s) {
+        if (done >= sd.max_steps) {
+            status = kSlotMaxSteps;
+            break;
+        }
+        if (clock_budget > 0) {
+            // time slice: every thread sees the same decision
+            if (threadIdx.x == 0) s_go = (long long)(wall_clock64() - s_t0) < clock_budget;
+            __syncthreads();
+            const int go = s_go;
+            __syncthreads();
+            if (!go) break;
+        }
+        bool ok = true;
+        for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
+            ok = node_moments_eos<LAT, NC, P>(kp, n, N, pops[cur], rref, rt, lnf) && ok;
+        if (!ok) s_bad = 1;
+        __syncthreads();
+        if (s_bad) {
+            status = kSlotNumeric;
+            break;
+        }
+        for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
+            node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, pops[cur], pops[1 - cur], rref, rt, lnf, fsum,
+                                                 false);
+        __syncthreads();
+        cur = 1 - cur;
+        ++done;
+        if (done % sd.check_every == 0) {
+            // rate residual against the snapshot of check_every steps ago
+            double mdiff[NC], mrho[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) mdiff[c] = mrho[c] = 0.0;
+            for (int n = threadIdx.x; n < dm.N; n += kServeBlock) {
+                P gv[NC][L::Q];
+                load_pops<L, NC, P>(pops[cur], n, N, gv);
+                double rho[NC], mov[NC];
+                densities<L, NC, P>(gv, rref, n, N, rho, mov);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    mdiff[c] = fmax(mdiff[c], fabs(rho[c] - snap[(size_t)c * N + n]));
+                    mrho[c] = fmax(mrho[c], fabs(rho[c]));
+                    snap[(size_t)c * N + n] = rho[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                for (int off = 32; off > 0; off >>= 1) {
+                    mdiff[c] = fmax(mdiff[c], __shfl_xor(mdiff[c], off));
+                    mrho[c] = fmax(mrho[c], __shfl_xor(mrho[c], off));
+                }
+            const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    s_red[c][wave] = mdiff[c];
+                    s_red[NC + c][wave] = mrho[c];
+                }
+            __syncthreads();
+            double r = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double md = 0.0, mr = 0.0;
+                for (int w = 0; w < kServeBlock / 64; ++w) {
+                    md = fmax(md, s_red[c][w]);
+                    mr = fmax(mr, s_red[NC + c][w]);
+                }
+                const double rc = md / ((double)sd.check_every * mr);
+                r = (rc > r || rc != rc) ? rc : r;
+            }
+            residual = r;
+            __syncthreads();
+            if (!(r == r)) {
+                status = kSlotNumeric;
+                break;
+            }
+            if (r < sd.tol) {
+                status = kSlotConverged;
+                break;
+            }
+        }
+    }
+    if (status == kSlotRunning && done >= sd.max_steps) status = kSlotMaxSteps;
+    if (threadIdx.x == 0) {
+        descs[blockIdx.x].steps = done;
+        descs[blockIdx.x].cur = cur;
+        descs[blockIdx.x].residual = residual;
+        descs[blockIdx.x].status = status;
+    }
+}
+
+hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs, int nslots,
+                             long long steps, long long clock_budget) {
+    if (nslots <= 0) return hipSuccess;
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        auto go = [&](auto bsc) {
+            constexpr int BS = decltype(bsc)::value;
+            if (lc.mrt)
+                k_serve_tick<LAT, NC, P, true, BS><<<nslots, BS, 0, lc.stream>>>(kp, pool, descs, steps, clock_budget);
+            else
+                k_serve_tick<LAT, NC, P, false, BS><<<nslots, BS, 0, lc.stream>>>(kp, pool, descs, steps, clock_budget);
+        };
+        if (lc.serve_block >= 1024)
+            go(std::integral_constant<int, 1024>{});
+        else if (lc.serve_block >= 512)
+            go(std::integral_constant<int, 512>{});
+        else
+            go(std::integral_constant<int, 256>{});
     });
     return hipGetLastError();
 }

@@ -17,6 +17,7 @@ struct LaunchCfg {
     int block_k2 = 64;      // threads per block of the collide/stream kernel
     bool xcd_remap = true;  // XCD-contiguous block order
     bool nt_store = false;  // non-temporal population stores
+    int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
@@ -35,5 +36,27 @@ hipError_t launch_export_pops(const LaunchCfg& lc, const KParams& kp, const void
 hipError_t launch_reduce(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                          double* snap, double* partial, double* out);
 int reduce_blocks(int N);
+hipError_t launch_snapshot(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref, double* snap);
+
+// One in-flight request of the batched server (device copy updated each tick).
+struct SlotDesc {
+    int nx, ny, nz, N;
+    long long off_pop[2];     // byte offsets into the pool
+    long long off_rt, off_lnf, off_fsum, off_rref, off_snap;
+    long long steps;          // steps done
+    long long max_steps;
+    long long check_every;
+    double tol;
+    double residual;
+    int cur;                  // population buffer holding the current state
+    int status;               // kSlotRunning, kSlotConverged, kSlotMaxSteps, kSlotNumeric
+};
+enum { kSlotRunning = 0, kSlotConverged = 1, kSlotMaxSteps = 2, kSlotNumeric = 3 };
+
+// Advance every slot of descs[0..nslots) by up to `steps` steps, one workgroup
+// per slot, each stopping early once clock_budget ticks of the device wall
+// clock have passed (<= 0: no limit); descs is updated in place.
+hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs,
+                             int nslots, long long steps, long long clock_budget);
 
 }  // namespace fl

@@ -70,6 +70,17 @@ SIGNATURES = {
     "fl_state_bytes": (C.c_int, [_VP, C.POINTER(C.c_size_t)]),
     "fl_get_state_raw": (C.c_int, [_VP, _VP, C.c_size_t]),
     "fl_set_state_raw": (C.c_int, [_VP, _VP, C.c_size_t]),
+    "fl_server_create": (C.c_int, [C.POINTER(fl_params), C.c_size_t, C.c_int, _VP, C.POINTER(_VP)]),
+    "fl_server_destroy": (None, [_VP]),
+    "fl_server_last_error": (C.c_char_p, [_VP]),
+    "fl_server_request_bytes": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "fl_server_submit": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _DP, C.c_double, C.c_long, C.c_long,
+                                   C.POINTER(C.c_uint64)]),
+    "fl_server_tick": (C.c_int, [_VP, C.c_long, C.c_double, C.POINTER(C.c_int)]),
+    "fl_server_poll": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int, C.POINTER(C.c_int)]),
+    "fl_server_result": (C.c_int, [_VP, C.c_uint64, _DP, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]),
+    "fl_server_info": (C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
+                                 C.POINTER(C.c_size_t)]),
 }
 
 
@@ -101,6 +112,9 @@ class Params:
     def __init__(self, components, T, shape, lattice="D2Q9", kij=None, R=1.0, eos="PR",
                  collision="BGK", tau=1.0, mrt_rates=None, precision="fp64", force_time_level=0):
         nc = len(components)
+        self._args = dict(components=[dict(c) for c in components], T=T, lattice=lattice, kij=kij, R=R,
+                          eos=eos, collision=collision, tau=tau, mrt_rates=mrt_rates,
+                          precision=precision, force_time_level=force_time_level)
         self._comp = (fl_component * nc)(*[fl_component(c["Tc"], c["Pc"], c["omega"], c["M"], c["kappa"])
                                            for c in components])
         self._kij = None
@@ -139,6 +153,14 @@ class Params:
         comps, kij, T = w.thermo()
         return cls(comps, T, shape or w.shape, lattice=w.lattice, kij=kij, collision=w.collision,
                    tau=w.tau, precision=precision or w.precision, **kw)
+
+    def with_shape(self, shape, precision=None):
+        """Same problem on another lattice shape (and optionally precision)."""
+        kw = dict(self._args)
+        if precision is not None:
+            kw["precision"] = precision
+        comps, T = kw.pop("components"), kw.pop("T")
+        return Params(comps, T, shape, **kw)
 
     def validate(self):
         return load().fl_validate(C.byref(self.c))
@@ -263,3 +285,86 @@ class Solver:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(self.lib.fl_set_state_raw(self.h, buf.ctypes.data_as(_VP), C.c_size_t(buf.size)),
                     "fl_set_state_raw")
+
+
+class Server:
+    """Batched server (fl_server_*): many independent lattices, one batched
+    kernel launch per tick.  The server owns its pool of device memory."""
+
+    def __init__(self, params: Params, pool_bytes, max_slots=512):
+        import torch  # the current torch stream carries the server's work
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the fuglbm server runs only on the HIP device")
+        self.lib = load()
+        self.p = params
+        self.stream = torch.cuda.current_stream()
+        h = _VP()
+        st = self.lib.fl_server_create(C.byref(params.c), C.c_size_t(int(pool_bytes)), int(max_slots),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != FL_OK:
+            raise FLError(st, "fl_server_create failed")
+        self.h = h
+
+    def _check(self, st, what):
+        if st not in (FL_OK,):
+            msg = self.lib.fl_server_last_error(self.h)
+            raise FLError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def request_bytes(self, shape):
+        nx, ny, nz = (tuple(shape) + (1,))[:3]
+        b = C.c_size_t(0)
+        self._check(self.lib.fl_server_request_bytes(self.h, nx, ny, nz, C.byref(b)), "request_bytes")
+        return b.value
+
+    def submit(self, rho_molar, shape, tol, check_every, max_steps):
+        """Returns the request id, or None when the server cannot admit it now."""
+        nx, ny, nz = (tuple(shape) + (1,))[:3]
+        r = np.ascontiguousarray(np.asarray(rho_molar, dtype=np.float64).reshape(self.p.ncomp, -1))
+        rid = C.c_uint64(0)
+        st = self.lib.fl_server_submit(self.h, nx, ny, nz, _dp(r), float(tol), int(check_every),
+                                       int(max_steps), C.byref(rid))
+        if st == FL_EAGAIN:
+            return None
+        self._check(st, "fl_server_submit")
+        return rid.value
+
+    def tick(self, steps, max_ms=0.0):
+        """Advance every running request by up to `steps` steps or max_ms of
+        device time (<= 0: no limit); returns the number still running."""
+        a = C.c_int(0)
+        self._check(self.lib.fl_server_tick(self.h, int(steps), float(max_ms), C.byref(a)), "fl_server_tick")
+        return a.value
+
+    def poll(self, cap=4096):
+        ids = (C.c_uint64 * cap)()
+        n = C.c_int(0)
+        self._check(self.lib.fl_server_poll(self.h, ids, cap, C.byref(n)), "fl_server_poll")
+        return [ids[i] for i in range(n.value)]
+
+    def result(self, rid, n_nodes):
+        rho = np.zeros((self.p.ncomp, n_nodes))
+        steps = C.c_long(0)
+        res = C.c_double(0.0)
+        status = C.c_int(0)
+        self._check(self.lib.fl_server_result(self.h, C.c_uint64(rid), _dp(rho), C.byref(steps), C.byref(res),
+                                              C.byref(status)), "fl_server_result")
+        return rho, steps.value, res.value, status.value
+
+    def info(self):
+        a, f = C.c_int(0), C.c_int(0)
+        used, tot = C.c_size_t(0), C.c_size_t(0)
+        self._check(self.lib.fl_server_info(self.h, C.byref(a), C.byref(f), C.byref(used), C.byref(tot)),
+                    "fl_server_info")
+        return {"active": a.value, "free_slots": f.value, "pool_used": used.value, "pool_total": tot.value}

@@ -1,0 +1,105 @@
+"""Request loop of the batched VLE server.
+
+Requests arrive as a seeded Poisson stream; a request is admitted when a
+server slot and enough pool memory are free (admission by HBM budget); every
+tick advances all admitted, unfinished requests in one batched kernel launch;
+finished requests are collected and their latency (arrival to collection)
+recorded.  The plain comparison path solves the same requests one after
+another with the single-lattice solver.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+
+import numpy as np
+
+from . import fuglbm as F
+from . import workloads as wl
+
+
+def request_field(req, W=4.0, SV=0.5):
+    """Initial molar densities of one request (tanh slab, eq. eqInit)."""
+    L, ny = req["L"], req["ny"]
+    x = np.arange(L, dtype=np.float64)
+    prof = np.stack([wl.slab_profile(x, L, req["rho_L"][i], req["rho_V"][i], SV, W)
+                     for i in range(len(req["rho_L"]))])
+    return np.ascontiguousarray(np.repeat(prof[:, None, :], ny, axis=1))
+
+
+def poisson_arrivals(n, rate, seed=0):
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def percentile(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else float("nan")
+
+
+def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms=20.0,
+          time_limit_s=None, on_result=None):
+    """Run the request stream through the server.  Wall-clock times in seconds
+    from the start; arrivals[i] is request i's arrival time."""
+    order = np.argsort(arrivals)
+    pending = deque(int(i) for i in order)
+    inflight = {}
+    done = []
+    t0 = time.perf_counter()
+    ticks = 0
+    rejected_admissions = 0
+    while pending or inflight:
+        now = time.perf_counter() - t0
+        while pending and arrivals[pending[0]] <= now:
+            i = pending[0]
+            r = reqs[i]
+            rid = server.submit(request_field(r), (r["L"], r["ny"]), tol, check_every, max_steps)
+            if rid is None:
+                rejected_admissions += 1
+                break
+            pending.popleft()
+            inflight[rid] = i
+        if not inflight:
+            if pending:
+                wait = arrivals[pending[0]] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+            continue
+        server.tick(max_steps, tick_ms)
+        ticks += 1
+        for rid in server.poll():
+            i = inflight.pop(rid)
+            r = reqs[i]
+            rho, steps, res, status = server.result(rid, r["L"] * r["ny"])
+            t = time.perf_counter() - t0
+            rec = {"i": i, "L": r["L"], "steps": steps, "residual": res, "status": status,
+                   "arrival": float(arrivals[i]), "done": t, "latency": t - float(arrivals[i])}
+            done.append(rec)
+            if on_result:
+                on_result(rec, rho)
+        if time_limit_s and time.perf_counter() - t0 > time_limit_s:
+            break
+    wall = time.perf_counter() - t0
+    lat = [d["latency"] for d in done]
+    span = (max(d["done"] for d in done) - min(d["arrival"] for d in done)) if done else float("nan")
+    return {
+        "requests": len(reqs), "completed": len(done),
+        "converged": sum(d["status"] == F.FL_OK for d in done),
+        "max_steps_reached": sum(d["status"] == F.FL_ENOTCONV for d in done),
+        "numeric_failures": sum(d["status"] == F.FL_ENUMERIC for d in done),
+        "solves_per_s": len(done) / span if done else 0.0,
+        "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
+        "wall_s": wall, "ticks": ticks, "admission_waits": rejected_admissions,
+        "records": done,
+    }
+
+
+def solve_plain(params: F.Params, req, tol, check_every, max_steps, precision="fp64"):
+    """One request with the single-lattice solver (two kernels per step)."""
+    s = F.Solver(params.with_shape((req["L"], req["ny"]), precision=precision))
+    s.set_state(request_field(req))
+    t = time.perf_counter()
+    conv, steps, res = s.run_until(tol, check_every, max_steps)
+    dt = time.perf_counter() - t
+    rho = s.fields()["rho_molar"]
+    s.close()
+    return rho, steps, res, conv, dt

@@ -1,0 +1,168 @@
+"""Batched server (fl_server_*) on the GPU, through the C ABI.
+
+* each request's result equals the single-lattice solver's (same kernels' node
+  arithmetic, same residual checks) bitwise;
+* a request's result is bitwise the same alone and in a mix, whatever the tick
+  size (continuous batching does not change per-request arithmetic);
+* admission is bounded by the pool budget and the slot count;
+* a request that leaves the EOS domain fails alone;
+* the FP32-population server agrees with the FP64 oracle within 1e-4.
+"""
+import numpy as np
+import pytest
+
+from paper_2212_10680_amd import fuglbm as F
+from paper_2212_10680_amd import serving
+from paper_2212_10680_amd import workloads as wl
+
+from _util import oracle_for, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def base_params(precision="fp32"):
+    return F.Params.from_workload(wl.WORKLOADS["serving_binary_2d"], precision=precision)
+
+
+def some_requests(n, seed=0):
+    reqs, _ = wl.serving_requests(n=n, seed=seed, L_min=32, L_max=160)
+    return reqs
+
+
+def run_server(p, reqs, tol, check, max_steps, tick, pool=1 << 28, order=None):
+    srv = F.Server(p, pool_bytes=pool, max_slots=64)
+    ids = {}
+    for i in (order if order is not None else range(len(reqs))):
+        r = reqs[i]
+        rid = srv.submit(serving.request_field(r), (r["L"], r["ny"]), tol, check, max_steps)
+        assert rid is not None
+        ids[rid] = i
+    out = {}
+    while len(out) < len(reqs):
+        srv.tick(tick)
+        for rid in srv.poll():
+            i = ids[rid]
+            out[i] = srv.result(rid, reqs[i]["L"] * reqs[i]["ny"])
+    srv.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_server_equals_plain_solver_bitwise(precision):
+    announce(f"server vs plain solver ({precision})")
+    p = base_params(precision)
+    reqs = some_requests(3)
+    got = run_server(p, reqs, tol=0.0, check=250, max_steps=1500, tick=400)
+    for i, r in enumerate(reqs):
+        rho, steps, res, status = got[i]
+        assert steps == 1500 and status == F.FL_ENOTCONV
+        rho_p, steps_p, res_p, conv, _ = serving.solve_plain(p, r, 0.0, 250, 1500, precision=precision)
+        assert steps_p == 1500 and not conv
+        assert np.array_equal(rho, rho_p.reshape(rho.shape)), i
+        assert res == res_p
+
+
+def test_alone_vs_mix_bitwise():
+    announce("alone vs mix")
+    p = base_params("fp32")
+    reqs = some_requests(6, seed=3)
+    alone = run_server(p, reqs[:1], tol=1e-9, check=200, max_steps=3000, tick=3000)
+    mix = run_server(p, reqs, tol=1e-9, check=200, max_steps=3000, tick=137, order=[3, 1, 0, 5, 2, 4])
+    a, m = alone[0], mix[0]
+    assert a[1] == m[1] and a[3] == m[3] and a[2] == m[2]
+    assert np.array_equal(a[0], m[0])
+
+
+def test_admission_by_pool_budget():
+    announce("admission budget")
+    p = base_params("fp32")
+    req = dict(some_requests(1)[0], L=128)
+    srv = F.Server(p, pool_bytes=1 << 20, max_slots=8)
+    need = srv.request_bytes((128, 8))
+    total = srv.info()["pool_total"]
+    fits = total // need
+    assert 1 <= fits < 8
+    ids = []
+    while True:
+        rid = srv.submit(serving.request_field(req), (128, 8), 0.0, 100, 200)
+        if rid is None:
+            break
+        ids.append(rid)
+        assert len(ids) <= fits
+    assert len(ids) == fits
+    info = srv.info()
+    assert info["pool_used"] == fits * need and info["active"] == fits
+    srv.tick(500)
+    assert srv.poll() and len(srv.poll()) == fits
+    srv.result(ids[0], 128 * 8)
+    assert srv.submit(serving.request_field(req), (128, 8), 0.0, 100, 200) is not None
+    srv.close()
+
+
+def test_slot_limit():
+    announce("slot limit")
+    p = base_params("fp32")
+    req = some_requests(1)[0]
+    srv = F.Server(p, pool_bytes=1 << 26, max_slots=2)
+    f = serving.request_field(req)
+    assert srv.submit(f, (req["L"], 8), 0.0, 100, 100) is not None
+    assert srv.submit(f, (req["L"], 8), 0.0, 100, 100) is not None
+    assert srv.submit(f, (req["L"], 8), 0.0, 100, 100) is None
+    srv.close()
+
+
+def test_failure_isolation():
+    """A request driven out of the EOS domain fails alone; others are unaffected."""
+    announce("failure isolation")
+    p = base_params("fp32")
+    reqs = some_requests(3, seed=5)
+    good = run_server(p, reqs, tol=0.0, check=100, max_steps=600, tick=600)
+    srv = F.Server(p, pool_bytes=1 << 26, max_slots=8)
+    ids = {}
+    for i, r in enumerate(reqs):
+        ids[srv.submit(serving.request_field(r), (r["L"], 8), 0.0, 100, 600)] = i
+    rng = np.random.default_rng(0)
+    # in the EOS domain (rho~ b_m <= 0.90) but far from any stable state: the
+    # FP64 oracle leaves the domain at its second step
+    bad = np.stack([np.full((8, 32), 1.0), np.full((8, 32), 8.0)]) * (1 + 0.05 * rng.uniform(-1, 1, (2, 8, 32)))
+    bad_id = srv.submit(bad, (32, 8), 0.0, 100, 600)
+    assert bad_id is not None
+    res = {}
+    while len(res) < 4:
+        srv.tick(600)
+        for rid in srv.poll():
+            n = 32 * 8 if rid == bad_id else reqs[ids[rid]]["L"] * 8
+            res[rid] = srv.result(rid, n)
+    assert res[bad_id][3] == F.FL_ENUMERIC
+    for rid, i in ids.items():
+        assert np.array_equal(res[rid][0], good[i][0])
+    srv.close()
+
+
+def test_server_fp32_vs_oracle():
+    announce("server fp32 vs fp64 oracle")
+    p = base_params("fp32")
+    r = dict(some_requests(1, seed=2)[0], L=96)
+    out = run_server(p, [r], tol=0.0, check=500, max_steps=2000, tick=2000)
+    rho = out[0][0]
+    w = wl.WORKLOADS["serving_binary_2d"].scaled((96, 8))
+    o = oracle_for(w)
+    o.init(serving.request_field(r).reshape(2, -1))
+    o.run(2000)
+    err = rel(rho.reshape(2, -1), o.fields()["rho_molar"])
+    print(f"  rel diff {err:.2e}", flush=True)
+    assert err < 1e-4
+
+
+def test_convergence_status():
+    announce("converges")
+    p = base_params("fp32")
+    r = dict(some_requests(1, seed=4)[0], L=32, ny=2)
+    out = run_server(p, [r], tol=1e-8, check=500, max_steps=200000, tick=5000)
+    rho, steps, res, status = out[0]
+    print(f"  steps {steps} residual {res:.2e}", flush=True)
+    assert status == F.FL_OK and res < 1e-8 and steps % 500 == 0
