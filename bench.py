@@ -49,7 +49,8 @@ def algorithmic_bytes(w, precision):
     k_moments_eos: read every population, write rho~_i and ln f_i (FP64).
     k_collide_stream: read and write every population, read rho~_i and ln f_i
     once (the stencil re-reads are cache traffic), read and write the previous
-    force sum (D FP64).  The FP32 form also reads the rest-population reference.
+    force sum (D values).  The FP32 form also reads the rest-population reference.
+    k_fused_step: the whole step, i.e. the per-node-step figure.
     """
     Q = 9 if w.lattice == "D2Q9" else 19
     D = w.D
@@ -60,9 +61,10 @@ def algorithmic_bytes(w, precision):
     k1 = pops + ref + 2 * 8 * nc
     k2 = 2 * pops + ref + 2 * 8 * nc + 2 * s * D
     # per-node-step figure: populations once in and out, the FP64 densities and
-    # ln f once each way, the force history (population precision) once each way
-    step = 2 * pops + 32 * nc + 2 * s * D
-    return {"k_moments_eos": k1, "k_collide_stream": k2, "step": step}
+    # ln f once each way, the force history (population precision) once each
+    # way, and the FP32 form's rest-population reference once
+    step = 2 * pops + 32 * nc + 2 * s * D + ref
+    return {"k_moments_eos": k1, "k_collide_stream": k2, "k_fused_step": step, "step": step}
 
 
 def stored_traffic(kernel, nodes):

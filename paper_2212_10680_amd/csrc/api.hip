@@ -33,7 +33,12 @@ struct fl_solver {
     int cur = 0;
     double* rt = nullptr;
     double* lnf = nullptr;
-    void* fsum = nullptr;                  // force history, population precision
+    void* fsum[2] = {nullptr, nullptr};    // force history (population precision), double-buffered
+    int fcur = 0;
+    unsigned* counters = nullptr;          // per-XCD plane counters of the fused step
+    bool fused = false;                    // one-launch step in use
+    fl::FusedCfg fc{};
+    unsigned fused_launches = 0;
     float* rref = nullptr;
     double* snap = nullptr;
     double* out = nullptr;                 // (D + 1) * N scratch for field export
@@ -78,8 +83,10 @@ int lattice_dims(int lattice, int* D, int* Q) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+int xcd_placement_ok(hipStream_t stream);
+
 struct Layout {
-    size_t pop, rt, lnf, fsum, rref, snap, out, partial, red, err, total;
+    size_t pop, rt, lnf, fsum, rref, snap, out, partial, red, err, counters, total;
 };
 
 Layout layout_for(const fl_params* p) {
@@ -94,13 +101,15 @@ Layout layout_for(const fl_params* p) {
     L.pop = take(2 * nc * Q * N * es);
     L.rt = take(nc * N * 8);
     L.lnf = take(nc * N * 8);
-    L.fsum = take((size_t)D * N * es);
+    L.fsum = take(2 * (size_t)D * N * es);
     L.rref = take(p->precision == FL_FP64 ? 0 : nc * N * 4);
     L.snap = take(nc * N * 8);
     L.out = take((size_t)(D + 1) * N * 8);
     L.partial = take((size_t)fl::reduce_blocks((int)N) * 3 * nc * 8);
     L.red = take(3 * nc * 8);
     L.err = take(256);
+    const int planes = D == 3 ? p->nz : p->ny;
+    L.counters = take((size_t)8 * ((planes + 7) / 8 + 8) * sizeof(unsigned));
     L.total = off;
     return L;
 }
@@ -190,6 +199,17 @@ int setup(fl_solver* s, const fl_params* p) {
     s->lc.nc = p->ncomp;
     s->lc.precision = p->precision;
     s->lc.mrt = p->collision == FL_MRT;
+    {
+        // fused-step geometry: planes along the slowest axis
+        const int planes = s->D == 3 ? p->nz : p->ny;
+        const int S = s->D == 3 ? p->nx * p->ny : p->nx;
+        s->fc.planes = planes;
+        s->fc.S = S;
+        s->fc.tpp = (S + 255) / 256;
+        s->fc.cstride = (planes + 7) / 8 + 8;
+        s->fc.target = 0;
+        s->fc.spin_limit = 1 << 24;
+    }
     // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0"
     if (const char* t = std::getenv("FUGLBM_TUNE")) {
         int v;
@@ -202,6 +222,7 @@ int setup(fl_solver* s, const fl_params* p) {
         if ((q = std::strstr(t, "nt=")) && std::sscanf(q + 3, "%d", &v) == 1) s->lc.nt_store = v != 0;
         if ((q = std::strstr(t, "serve=")) && std::sscanf(q + 6, "%d", &v) == 1 && (v == 256 || v == 512 || v == 1024))
             s->lc.serve_block = v;
+        if ((q = std::strstr(t, "fused=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.fused = v != 0;
     }
     return FL_OK;
 }
@@ -214,18 +235,24 @@ int carve(fl_solver* s, void* base) {
     s->pop[1] = b + L.pop + half;
     s->rt = (double*)(b + L.rt);
     s->lnf = (double*)(b + L.lnf);
-    s->fsum = (void*)(b + L.fsum);
+    s->fsum[0] = (void*)(b + L.fsum);
+    s->fsum[1] = (void*)(b + L.fsum + (size_t)s->D * s->N * s->pop_elem);
+    s->counters = (unsigned*)(b + L.counters);
     s->rref = s->prm.precision == FL_FP64 ? nullptr : (float*)(b + L.rref);
     s->snap = (double*)(b + L.snap);
     s->out = (double*)(b + L.out);
     s->partial = (double*)(b + L.partial);
     s->red = (double*)(b + L.red);
     s->err = (int*)(b + L.err);
+    // one-launch step: needs >= 8 planes per XCD (halo recompute <= 50 %) and
+    // planes of whole 128-byte lines of the FP64 density arrays
+    s->fused = s->lc.fused && s->fc.planes >= 64 && s->fc.S % 16 == 0 && xcd_placement_ok(s->stream);
     HIP_TRY(s, hipHostMalloc((void**)&s->h_err, sizeof(int) * 4, hipHostMallocDefault));
     HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
     HIP_TRY(s, hipMemsetAsync(s->err, 0, 256, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->pop[0], 0, 2 * half, s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->fsum, 0, (size_t)s->D * s->N * s->pop_elem, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->fsum[0], 0, 2 * (size_t)s->D * s->N * s->pop_elem, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->counters, 0, (size_t)8 * s->fc.cstride * sizeof(unsigned), s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return FL_OK;
 }
@@ -235,8 +262,14 @@ int check_err(fl_solver* s) {
     HIP_TRY(s, hipMemcpyAsync(s->h_err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     if (*s->h_err) {
+        const int flags = *s->h_err;
         HIP_TRY(s, hipMemsetAsync(s->err, 0, sizeof(int), s->stream));
         HIP_TRY(s, hipStreamSynchronize(s->stream));
+        if (flags & (fl::kErrXcd | fl::kErrWait)) {
+            s->fused = false;  // later steps use the two-kernel path
+            return fail(s, FL_EDEVICE, (flags & fl::kErrXcd) ? "fused step: a block ran on an unexpected XCD"
+                                                              : "fused step: a dependency wait timed out");
+        }
         return fail(s, FL_ENUMERIC, "a node left the EOS domain (rho~_i <= 0, rho~ b_m >= 1 or non-finite)");
     }
     return FL_OK;
@@ -248,13 +281,45 @@ int one_step(fl_solver* s, hipEvent_t* ev) {
     LaunchCfg lc = s->lc;
     lc.stream = s->stream;
     if (ev) HIP_TRY(s, hipEventRecord(ev[0], s->stream));
-    HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
-    if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
-    HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum));
-    if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
+    if (s->fused) {
+        fl::FusedCfg fc = s->fc;
+        fc.target = (unsigned)fc.tpp * (s->fused_launches + 1u);
+        HIP_TRY(s, fl::launch_fused_step(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
+                                         s->fsum[1 - s->fcur], s->counters, s->err, fc));
+        s->fused_launches += 1;
+        if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
+    } else {
+        HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
+        if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
+        HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
+                                             s->fsum[1 - s->fcur]));
+        if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
+    }
     s->cur = 1 - s->cur;
+    s->fcur = 1 - s->fcur;
     s->steps += 1;
     return FL_OK;
+}
+
+// Blocks of one launch run on XCD (block index % 8): checked once per process.
+int xcd_placement_ok(hipStream_t stream) {
+    static int verdict = -1;
+    if (verdict >= 0) return verdict;
+    const int nb = 4096;
+    int* d = nullptr;
+    std::vector<int> h(nb, -1);
+    verdict = 0;
+    if (hipMalloc(&d, nb * sizeof(int)) != hipSuccess) { (void)hipGetLastError(); return verdict; }
+    if (fl::launch_xcd_ids(d, nb, stream) == hipSuccess &&
+        hipMemcpyAsync(h.data(), d, nb * sizeof(int), hipMemcpyDeviceToHost, stream) == hipSuccess &&
+        hipStreamSynchronize(stream) == hipSuccess) {
+        verdict = 1;
+        for (int b = 0; b < nb; ++b)
+            if (h[b] != b % 8) verdict = 0;
+    }
+    (void)hipFree(d);
+    (void)hipGetLastError();
+    return verdict;
 }
 
 int reduce(fl_solver* s, bool with_snap) {
@@ -340,7 +405,7 @@ static int create_common(const fl_params* p, void* mem, size_t bytes, void* stre
         s->own_stream = true;
         e = hipMalloc(&s->mem, need);
         if (e != hipSuccess) {
-            hipStreamDestroy(s->stream);
+            (void)hipStreamDestroy(s->stream);
             delete s;
             (void)hipGetLastError();
             return FL_ENOMEM;
@@ -412,7 +477,10 @@ int fl_set_state(fl_solver* s, const double* rho_molar, const double* u) {
     LaunchCfg lc = s->lc;
     lc.stream = s->stream;
     s->cur = 0;
-    HIP_TRY(s, fl::launch_init(lc, s->kp, s->rt, u ? s->out : nullptr, s->pop[0], s->rref, s->fsum));
+    s->fcur = 0;
+    s->fused_launches = 0;
+    HIP_TRY(s, hipMemsetAsync(s->counters, 0, (size_t)8 * s->fc.cstride * sizeof(unsigned), s->stream));
+    HIP_TRY(s, fl::launch_init(lc, s->kp, s->rt, u ? s->out : nullptr, s->pop[0], s->rref, s->fsum[0]));
     HIP_TRY(s, hipMemsetAsync(s->err, 0, sizeof(int), s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->steps = 0;
@@ -432,6 +500,8 @@ int fl_step(fl_solver* s, long nsteps) {
 int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names, int* nkernels) {
     if (!s || nsteps < 0 || !kernel_ms || !nkernels || *nkernels < 2) return FL_EINVAL;
     static const char* kNames[2] = {"k_moments_eos", "k_collide_stream"};
+    static const char* kFused[1] = {"k_fused_step"};
+    const bool fused = s->fused;
     const long chunk = 256;
     std::vector<hipEvent_t> ev(3 * chunk);
     for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
@@ -446,17 +516,23 @@ int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** nam
         for (long k = 0; k < m; ++k) {
             float a = 0.f, b = 0.f;
             (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-            (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+            if (!fused) (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
             acc[0] += a;
             acc[1] += b;
         }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != FL_OK) return rc;
-    kernel_ms[0] = acc[0];
-    kernel_ms[1] = acc[1];
-    if (names) { names[0] = kNames[0]; names[1] = kNames[1]; }
-    *nkernels = 2;
+    if (fused) {
+        kernel_ms[0] = acc[0];
+        if (names) names[0] = kFused[0];
+        *nkernels = 1;
+    } else {
+        kernel_ms[0] = acc[0];
+        kernel_ms[1] = acc[1];
+        if (names) { names[0] = kNames[0]; names[1] = kNames[1]; }
+        *nkernels = 2;
+    }
     return check_err(s);
 }
 
@@ -471,7 +547,7 @@ int fl_get_fields(fl_solver* s, double* rho_molar, double* u, double* p, double*
     // the exported densities and ln f; out holds u then p.
     double* d_u = s->out;
     double* d_p = s->out + (size_t)s->D * N;
-    HIP_TRY(s, fl::launch_fields(lc, s->kp, s->pop[s->cur], s->rref, s->fsum, s->rt, d_u, d_p, s->lnf));
+    HIP_TRY(s, fl::launch_fields(lc, s->kp, s->pop[s->cur], s->rref, s->fsum[s->fcur], s->rt, d_u, d_p, s->lnf));
     if (rho_molar) HIP_TRY(s, hipMemcpyAsync(rho_molar, s->rt, sizeof(double) * s->nc * N, hipMemcpyDeviceToHost, s->stream));
     if (u) HIP_TRY(s, hipMemcpyAsync(u, d_u, sizeof(double) * s->D * N, hipMemcpyDeviceToHost, s->stream));
     if (p) HIP_TRY(s, hipMemcpyAsync(p, d_p, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream));
@@ -551,7 +627,7 @@ int fl_get_state_raw(fl_solver* s, void* host_buf, size_t bytes) {
     const size_t pb = s->nc * s->Q * s->N * s->pop_elem;
     HIP_TRY(s, hipMemcpyAsync(b + off, s->pop[s->cur], pb, hipMemcpyDeviceToHost, s->stream));
     off += pb;
-    HIP_TRY(s, hipMemcpyAsync(b + off, s->fsum, s->D * s->N * s->pop_elem, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(b + off, s->fsum[s->fcur], s->D * s->N * s->pop_elem, hipMemcpyDeviceToHost, s->stream));
     off += s->D * s->N * s->pop_elem;
     if (s->rref) HIP_TRY(s, hipMemcpyAsync(b + off, s->rref, s->nc * s->N * 4, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -568,9 +644,12 @@ int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
     size_t off = 16;
     const size_t pb = s->nc * s->Q * s->N * s->pop_elem;
     s->cur = 0;
+    s->fcur = 0;
+    s->fused_launches = 0;
+    HIP_TRY(s, hipMemsetAsync(s->counters, 0, (size_t)8 * s->fc.cstride * sizeof(unsigned), s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->pop[0], b + off, pb, hipMemcpyHostToDevice, s->stream));
     off += pb;
-    HIP_TRY(s, hipMemcpyAsync(s->fsum, b + off, s->D * s->N * s->pop_elem, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->fsum[0], b + off, s->D * s->N * s->pop_elem, hipMemcpyHostToDevice, s->stream));
     off += s->D * s->N * s->pop_elem;
     if (s->rref) HIP_TRY(s, hipMemcpyAsync(s->rref, b + off, s->nc * s->N * 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));

@@ -4,7 +4,8 @@
 //   populations  g[c][a][n]   (P = double, or float in the FP32 form where the
 //                             rest slot a = 0 holds g_0 minus rref[c][n])
 //   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64)
-//   fsum[k][n]                sum_i F_i of the previous step (population precision)
+//   fsum[k][n]                sum_i F_i of the previous step (population precision;
+//                             read from one buffer, written to another)
 //   rref[c][n]                rest-population reference (FP32 form only)
 //
 // Step = k_moments_eos (steps 1-5: reads every population once, writes rt and
@@ -109,7 +110,7 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
                                                     const float* __restrict__ rref,
                                                     const double* __restrict__ rt,
                                                     const double* __restrict__ lnf,
-                                                    P* __restrict__ fsum, bool nt) {
+                                                    const P* fsum_in, P* fsum_out, bool nt) {
     using L = Lat<LAT>;
     constexpr int D = L::D, Q = L::Q;
     using T = P;  // collision precision
@@ -217,7 +218,7 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : (double)fsum[(size_t)k * N + n];
+        const double fk = kp.force_level ? Fs[k] : (double)fsum_in[(size_t)k * N + n];
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
 
@@ -236,7 +237,7 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
             store_pop(&gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])], out[a], nt);
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = (P)Fs[k];
+    for (int k = 0; k < D; ++k) fsum_out[(size_t)k * N + n] = (P)Fs[k];
 }
 
 template <int LAT, int NC, typename P, bool MRT>
@@ -245,11 +246,11 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
                                                         const float* __restrict__ rref,
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
-                                                        P* __restrict__ fsum, int xcd_chunk, int nt) {
+                                                        const P* fsum_in, P* fsum_out, int xcd_chunk, int nt) {
     const int n = node_index(xcd_chunk);
     if (n >= kp.N) return;
     const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
-    node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, g, gn, rref, rt, lnf, fsum, nt != 0);
+    node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
 }
 
 // ------------------------------------------------------------ initial state
@@ -487,7 +488,8 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
 }
 
 hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
-                                 const float* rref, const double* rt, const double* lnf, void* fsum) {
+                                 const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                 void* fsum_out) {
     const int bs = lc.block_k2;
     const int nb = (kp.N + bs - 1) / bs;
     const int ch = xcd_chunk_for(lc, nb);
@@ -496,10 +498,10 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
         FL_TYPES;
         if (lc.mrt)
             k_collide_stream<LAT, NC, P, true><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (P*)fsum, ch, nt);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt);
         else
             k_collide_stream<LAT, NC, P, false><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (P*)fsum, ch, nt);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt);
     });
     return hipGetLastError();
 }
@@ -570,6 +572,112 @@ hipError_t launch_snapshot(const LaunchCfg& lc, const KParams& kp, const void* g
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------- fused step
+// One launch per step.  The lattice is cut along its slowest axis into
+// planes; XCD k (hardware block b runs on XCD b % 8) owns a contiguous range
+// of planes [P0, P1).  Its workgroups first compute steps 1-5 (densities and
+// ln f) for one 256-node tile of the planes P0-2 .. P1+1 (the two halo planes
+// on each side are recomputed by both neighbouring XCDs, with identical
+// values) and count the tile in a per-plane counter of the XCD; then they run
+// steps 6-9 for a tile 5 planes earlier, after the counters of its planes
+// p-2 .. p+2 are complete.  Every wait is on tiles of lower-numbered blocks of
+// the same XCD, which were dispatched before, so the launch always drains;
+// the waits are also bounded.  The densities and ln f a tile reads were
+// written through the same XCD's L2 (plane sizes are whole 128-byte lines, so
+// no line is read before all of it is written), and the populations are read
+// a second time from the Infinity Cache instead of HBM.
+template <int LAT, int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256) void k_fused_step(KParams kp, const P* __restrict__ g, P* __restrict__ gn,
+                                                    const float* __restrict__ rref, double* __restrict__ rt,
+                                                    double* __restrict__ lnf, const P* fsum_in, P* fsum_out,
+                                                    unsigned* __restrict__ counters, int* __restrict__ err,
+                                                    FusedCfg fc) {
+    const int k = blockIdx.x & 7;
+    const int j = blockIdx.x >> 3;
+    if (threadIdx.x == 0) {
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        if ((int)(xcc & 0xf) != k) atomicOr(err, kErrXcd);
+    }
+    const int P0 = (int)((long long)k * fc.planes / 8);
+    const int P1 = (int)((long long)(k + 1) * fc.planes / 8);
+    const int np = P1 - P0;
+    unsigned* cnt = counters + (size_t)k * fc.cstride;
+    // steps 1-5 for A-tile j
+    if (j < (np + 4) * fc.tpp) {
+        const int al = j / fc.tpp, t = j - al * fc.tpp;
+        int gp = P0 - 2 + al;
+        gp = gp < 0 ? gp + fc.planes : (gp >= fc.planes ? gp - fc.planes : gp);
+        const int off = t * 256 + threadIdx.x;
+        if (off < fc.S && !node_moments_eos<LAT, NC, P>(kp, gp * fc.S + off, kp.N, g, rref, rt, lnf))
+            atomicOr(err, 1);
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the L2
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __hip_atomic_fetch_add(&cnt[al], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // steps 6-9 for B-tile j - 5 tpp
+    const int jb = j - 5 * fc.tpp;
+    if (jb >= 0 && jb < np * fc.tpp) {
+        const int bl = jb / fc.tpp, t = jb - bl * fc.tpp;
+        if (threadIdx.x == 0) {
+            for (int q = 0; q < 5; ++q) {
+                int spins = 0;
+                while ((int)(__hip_atomic_load(&cnt[bl + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                             fc.target) < 0) {
+                    if (++spins > fc.spin_limit) {
+                        atomicOr(err, kErrWait);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+        __syncthreads();
+        const int off = t * 256 + threadIdx.x;
+        if (off < fc.S) {
+            const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
+            node_collide_stream<LAT, NC, P, MRT>(kp, dm, (P0 + bl) * fc.S + off, g, gn, rref, rt, lnf, fsum_in,
+                                                 fsum_out, false);
+        }
+    }
+}
+
+hipError_t launch_fused_step(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn, const float* rref,
+                             double* rt, double* lnf, const void* fsum_in, void* fsum_out, unsigned* counters,
+                             int* err, const FusedCfg& fc) {
+    const int np_max = (fc.planes + 7) / 8;
+    const dim3 grid(8 * (np_max + 5) * fc.tpp);
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        if (lc.mrt)
+            k_fused_step<LAT, NC, P, true><<<grid, 256, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, counters, err, fc);
+        else
+            k_fused_step<LAT, NC, P, false><<<grid, 256, 0, lc.stream>>>(
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, counters, err, fc);
+    });
+    return hipGetLastError();
+}
+
+// Hardware XCD of every block of a grid (to check the b % 8 placement).
+__global__ void k_xcd_ids(int* out, int nblocks) {
+    if (threadIdx.x == 0 && (int)blockIdx.x < nblocks) {
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        out[blockIdx.x] = (int)(xcc & 0xf);
+    }
+}
+
+hipError_t launch_xcd_ids(int* out, int nblocks, hipStream_t stream) {
+    k_xcd_ids<<<nblocks, 64, 0, stream>>>(out, nblocks);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ batched server
 // One workgroup advances one request: the two phases of a step are separated
 // by workgroup barriers (phase B reads the densities and ln f that other
@@ -629,7 +737,7 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
             break;
         }
         for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
-            node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, pops[cur], pops[1 - cur], rref, rt, lnf, fsum,
+            node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, pops[cur], pops[1 - cur], rref, rt, lnf, fsum, fsum,
                                                  false);
         __syncthreads();
         cur = 1 - cur;

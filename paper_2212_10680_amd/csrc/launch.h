@@ -18,13 +18,30 @@ struct LaunchCfg {
     bool xcd_remap = true;  // XCD-contiguous block order
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
+    bool fused = true;      // one-launch step when the lattice allows it
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* rt, double* lnf, int* err);
-// fsum: force history, in the population precision
+// fsum_in/fsum_out: force history (population precision), previous and this step
 hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
-                                 const float* rref, const double* rt, const double* lnf, void* fsum);
+                                 const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                 void* fsum_out);
+
+// Geometry of the fused one-launch step (see k_fused_step).
+struct FusedCfg {
+    int planes;         // planes along the slowest lattice axis
+    int S;              // nodes per plane (multiple of 16)
+    int tpp;            // 256-node tiles per plane
+    int cstride;        // counters per XCD
+    unsigned target;    // counter value of a complete plane in this launch
+    int spin_limit;     // bound on every wait loop
+};
+enum { kErrDomain = 1, kErrXcd = 4, kErrWait = 8 };
+hipError_t launch_fused_step(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn, const float* rref,
+                             double* rt, double* lnf, const void* fsum_in, void* fsum_out, unsigned* counters,
+                             int* err, const FusedCfg& fc);
+hipError_t launch_xcd_ids(int* out, int nblocks, hipStream_t stream);
 hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
                        void* g, float* rref, void* fsum);
 hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
