@@ -46,9 +46,9 @@ def kernel_source_hash():
 def algorithmic_bytes(w, precision):
     """Algorithmic HBM bytes per node of each kernel of one step.
 
-    k_moments_eos: read every population, write rho~_i and ln f_i (FP64).
-    k_collide_stream: read and write every population, read rho~_i and ln f_i
-    once (the stencil re-reads are cache traffic), read and write the previous
+    k_moments_eos: read every population, write rho~_i, ln f_i and phi (FP64).
+    k_collide_stream: read and write every population, read rho~_i, ln f_i and
+    phi once (the stencil re-reads are cache traffic), read and write the previous
     force sum (D values).  The FP32 form also reads the rest-population reference.
     k_fused_step: the whole step, i.e. the per-node-step figure.
     """
@@ -58,12 +58,13 @@ def algorithmic_bytes(w, precision):
     s = 8 if precision == "fp64" else 4
     ref = 0 if precision == "fp64" else 4 * nc
     pops = Q * nc * s
-    k1 = pops + ref + 2 * 8 * nc
-    k2 = 2 * pops + ref + 2 * 8 * nc + 2 * s * D
-    # per-node-step figure: populations once in and out, the FP64 densities and
-    # ln f once each way, the force history (population precision) once each
-    # way, and the FP32 form's rest-population reference once
-    step = 2 * pops + 32 * nc + 2 * s * D + ref
+    aux = 8 * (2 * nc + 1)          # rho~_i, ln f_i and the interface field phi (FP64)
+    k1 = pops + ref + aux
+    k2 = 2 * pops + ref + aux + 2 * s * D
+    # per-node-step figure: populations once in and out, the FP64 densities,
+    # ln f and phi once each way, the force history (population precision) once
+    # each way, and the FP32 form's rest-population reference once
+    step = 2 * pops + 2 * aux + 2 * s * D + ref
     return {"k_moments_eos": k1, "k_collide_stream": k2, "k_fused_step": step, "step": step}
 
 
@@ -185,6 +186,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batched serving leg")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-max-steps", type=int, default=50000)
+    ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
+                    help="uniform: the workload's mean composition everywhere (a steady state; the "
+                         "per-step work does not depend on the state)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (PMC byte-counter scale)")
     args = ap.parse_args()
@@ -206,6 +210,10 @@ def main():
     p = F.Params.from_workload(w, precision=precision)
     solver = F.Solver(p)
     rho, u = wl.initial_field(w)
+    if args.state == "uniform":
+        rho = np.ascontiguousarray(np.broadcast_to(rho.reshape(w.ncomp, -1).mean(axis=1)[:, None],
+                                                   (w.ncomp, w.nodes)))
+        u = None
     solver.set_state(rho, u)
     print(f"[bench] {w.name} {w.lattice} {w.shape} nc={w.ncomp} {w.collision} tau={w.tau} {precision}",
           file=sys.stderr, flush=True)
@@ -271,7 +279,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 populations / f64 EOS" if precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "lattice": w.lattice, "shape": list(w.shape), "ncomp": w.ncomp,
+        "config": {"workload": w.name, "state": args.state, "lattice": w.lattice, "shape": list(w.shape),
+                   "ncomp": w.ncomp,
                    "collision": w.collision, "tau": w.tau, "precision": precision,
                    "node_MLUPS": round(nodes * args.steps / wall / 1e6, 1)},
         "roofline": roofline,

@@ -100,7 +100,7 @@ Layout layout_for(const fl_params* p) {
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     L.pop = take(2 * nc * Q * N * es);
     L.rt = take(nc * N * 8);
-    L.lnf = take(nc * N * 8);
+    L.lnf = take((nc + 1) * N * 8);   // ln f_i, then the interface field phi
     L.fsum = take(2 * (size_t)D * N * es);
     L.rref = take(p->precision == FL_FP64 ? 0 : nc * N * 4);
     L.snap = take(nc * N * 8);
@@ -108,8 +108,7 @@ Layout layout_for(const fl_params* p) {
     L.partial = take((size_t)fl::reduce_blocks((int)N) * 3 * nc * 8);
     L.red = take(3 * nc * 8);
     L.err = take(256);
-    const int planes = D == 3 ? p->nz : p->ny;
-    L.counters = take((size_t)8 * ((planes + 7) / 8 + 8) * sizeof(unsigned));
+    L.counters = take((size_t)8 * (p->nz + 8) * sizeof(unsigned));
     L.total = off;
     return L;
 }
@@ -144,6 +143,7 @@ void eos_constants(const fl_solver* s, KParams* kp) {
             kp->aa[i * nc + j] = std::sqrt(aa[i] * aa[j]) * (1.0 - s->kij[i * nc + j]);
             kp->kap[i * nc + j] = std::sqrt(s->comp[i].kappa * s->comp[j].kappa);
         }
+    for (int i = 0; i < nc; ++i) kp->sk[i] = std::sqrt(s->comp[i].kappa);
 }
 
 // Host copy of the device EOS domain test for fl_set_state.
@@ -200,15 +200,12 @@ int setup(fl_solver* s, const fl_params* p) {
     s->lc.precision = p->precision;
     s->lc.mrt = p->collision == FL_MRT;
     {
-        // fused-step geometry: planes along the slowest axis
-        const int planes = s->D == 3 ? p->nz : p->ny;
-        const int S = s->D == 3 ? p->nx * p->ny : p->nx;
-        s->fc.planes = planes;
-        s->fc.S = S;
-        s->fc.tpp = (S + 255) / 256;
-        s->fc.cstride = (planes + 7) / 8 + 8;
+        // fused-step geometry: each XCD owns ny/8 (+1) rows plus 4 halo rows
+        const int rowsA = (p->ny + 7) / 8 + 4;
+        s->fc.tpp = (rowsA * p->nx + 255) / 256;
+        s->fc.cstride = p->nz + 8;
         s->fc.target = 0;
-        s->fc.spin_limit = 1 << 24;
+        s->fc.spin_limit = 1 << 20;   // about 60 ms of s_sleep per wait
     }
     // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0"
     if (const char* t = std::getenv("FUGLBM_TUNE")) {
@@ -244,9 +241,10 @@ int carve(fl_solver* s, void* base) {
     s->partial = (double*)(b + L.partial);
     s->red = (double*)(b + L.red);
     s->err = (int*)(b + L.err);
-    // one-launch step: needs >= 8 planes per XCD (halo recompute <= 50 %) and
-    // planes of whole 128-byte lines of the FP64 density arrays
-    s->fused = s->lc.fused && s->fc.planes >= 64 && s->fc.S % 16 == 0 && xcd_placement_ok(s->stream);
+    // one-launch step: D3Q19, >= 8 rows per XCD (halo recompute <= 50 %), rows
+    // of whole 128-byte lines of the FP64 density arrays, blocks placed on XCD b % 8
+    s->fused = s->lc.fused && s->D == 3 && s->prm.ny >= 64 && s->prm.nx % 16 == 0 && s->prm.nz >= 4 &&
+               xcd_placement_ok(s->stream);
     HIP_TRY(s, hipHostMalloc((void**)&s->h_err, sizeof(int) * 4, hipHostMallocDefault));
     HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
     HIP_TRY(s, hipMemsetAsync(s->err, 0, 256, s->stream));
@@ -708,7 +706,7 @@ ReqLayout req_layout(const fl_solver& c, size_t N) {
     L.pop0 = take(pb);
     L.pop1 = take(pb);
     L.rt = take((size_t)c.nc * N * 8);
-    L.lnf = take((size_t)c.nc * N * 8);
+    L.lnf = take((size_t)(c.nc + 1) * N * 8);
     L.fsum = take((size_t)c.D * N * c.pop_elem);
     L.rref = take(c.prm.precision == FL_FP64 ? 0 : (size_t)c.nc * N * 4);
     L.snap = take((size_t)c.nc * N * 8);

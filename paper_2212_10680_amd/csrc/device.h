@@ -27,6 +27,7 @@ struct KParams {
     double M[kMaxComp];
     double aa[kMaxComp * kMaxComp];   // (a alpha)_ij
     double kap[kMaxComp * kMaxComp];  // kappa_ij = sqrt(kappa_i kappa_j)
+    double sk[kMaxComp];              // sqrt(kappa_i)
 };
 
 // ---------------------------------------------------------------- lattices

@@ -3,7 +3,8 @@
 // Layout in HBM (structure of arrays, node index n = x + nx*(y + ny*z)):
 //   populations  g[c][a][n]   (P = double, or float in the FP32 form where the
 //                             rest slot a = 0 holds g_0 minus rref[c][n])
-//   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64)
+//   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64);
+//                             plane c = N_c of lnf holds phi[n] = sum_j sqrt(kappa_j) rho~_j
 //   fsum[k][n]                sum_i F_i of the previous step (population precision;
 //                             read from one buffer, written to another)
 //   rref[c][n]                rest-population reference (FP32 form only)
@@ -86,8 +87,13 @@ __device__ __forceinline__ bool node_moments_eos(const KParams& kp, int n, size_
         rt[(size_t)c * N + n] = r[c];
     }
     const bool ok = eos_lnf<NC>(kp, r, lf, nullptr);
+    double phi = 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) lnf[(size_t)c * N + n] = lf[c];
+    for (int c = 0; c < NC; ++c) {
+        lnf[(size_t)c * N + n] = lf[c];
+        phi += kp.sk[c] * r[c];
+    }
+    lnf[(size_t)NC * N + n] = phi;
     return ok;
 }
 
@@ -134,63 +140,55 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
         dz = (k == 2) ? s : 0;
     };
 
-    // step 6: Laplacian of rho~_j at the 2D neighbours, then mu_I,i there
-    double mu[NC][2 * D];
-    double rc[NC];   // rho~_i at the node
-    double rnb[NC][2 * D];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) rc[j] = rt[(size_t)j * N + n];
-    double lap[NC][2 * D];
+    // step 6: interface potential.  With kappa_ij = sqrt(kappa_i kappa_j)
+    // (eqkappa), mu_I,i = -sum_j kappa_ij lap(rho~_j) = -sqrt(kappa_i) lap(phi)
+    // with phi = sum_j sqrt(kappa_j) rho~_j, written by the moments pass: one
+    // scalar Laplacian (eq2ndder per axis) at each of the 2D neighbours.
+    const double* phi = lnf + (size_t)NC * N;
+    double mh[2 * D];  // -lap(phi) at n + e_k (index 2k) and n - e_k (index 2k+1)
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             int cx, cy, cz;
             unit(k, s == 0 ? 1 : -1, cx, cy, cz);
-            const int ci = idx(cx, cy, cz);
+            const double p0 = phi[idx(cx, cy, cz)];
+            double acc = 0.0;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const double* r = rt + (size_t)j * N;
-                const double r0 = r[ci];
-                rnb[j][2 * k + s] = r0;
-                double acc = 0.0;
-#pragma unroll
-                for (int m = 0; m < D; ++m) {
-                    int mx, my, mz;
-                    unit(m, 1, mx, my, mz);
-                    acc += r[idx(cx + mx, cy + my, cz + mz)] - 2.0 * r0 + r[idx(cx - mx, cy - my, cz - mz)];
-                }
-                lap[j][2 * k + s] = acc;
+            for (int m = 0; m < D; ++m) {
+                int mx, my, mz;
+                unit(m, 1, mx, my, mz);
+                acc += phi[idx(cx + mx, cy + my, cz + mz)] - 2.0 * p0 + phi[idx(cx - mx, cy - my, cz - mz)];
             }
-        }
-#pragma unroll
-    for (int i = 0; i < NC; ++i)
-#pragma unroll
-        for (int q = 0; q < 2 * D; ++q) {
-            double m = 0.0;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) m -= kp.kap[i * NC + j] * lap[j][q];
-            mu[i][q] = m;
+            mh[2 * k + s] = -acc;
         }
 
-    // step 7: F_i = -rho~_i [RT D(ln f_i) + D(mu_I,i)], and grad rho_i
-    double F[NC][3], G[NC][3];
+    // step 7: F_i = -rho~_i [RT D(ln f_i) + D(mu_I,i)] (eq1stder), and grad rho_i.
+    // Evaluated in FP64, kept in the collision precision (the collision reads
+    // them there); their sum over components stays FP64.
+    T F[NC][3], G[NC][3];
+    double Fs[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
         const double* lf = lnf + (size_t)i * N;
+        const double* r = rt + (size_t)i * N;
+        const double rc = r[n];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            F[i][k] = 0.0;
-            G[i][k] = 0.0;
+            F[i][k] = T(0);
+            G[i][k] = T(0);
         }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             int px, py, pz;
             unit(k, 1, px, py, pz);
-            const double dl = (lf[idx(px, py, pz)] - lf[idx(-px, -py, -pz)]) / 2.0;
-            const double dm = (mu[i][2 * k] - mu[i][2 * k + 1]) / 2.0;
-            F[i][k] = -rc[i] * (kp.RT * dl + dm);
-            G[i][k] = kp.M[i] * (rnb[i][2 * k] - rnb[i][2 * k + 1]) / 2.0;
+            const int ip = idx(px, py, pz), im = idx(-px, -py, -pz);
+            const double dl = (lf[ip] - lf[im]) / 2.0;
+            const double dm = kp.sk[i] * (mh[2 * k] - mh[2 * k + 1]) / 2.0;
+            const double f = -rc * (kp.RT * dl + dm);
+            Fs[k] += f;
+            F[i][k] = T(f);
+            G[i][k] = T(kp.M[i] * (r[ip] - r[im]) / 2.0);
         }
     }
 
@@ -210,11 +208,6 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
             j[2] += (double)gv[c][a] * L::ez[a];
         }
     }
-    double Fs[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < NC; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Fs[k] += F[i][k];
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -228,8 +221,8 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
         CompState<T> cs;
         cs.rho = T(rho[c]);
         cs.ux = T(u[0]); cs.uy = T(u[1]); cs.uz = T(u[2]);
-        cs.Fx = T(F[c][0]); cs.Fy = T(F[c][1]); cs.Fz = T(F[c][2]);
-        cs.Gx = T(G[c][0]); cs.Gy = T(G[c][1]); cs.Gz = T(G[c][2]);
+        cs.Fx = F[c][0]; cs.Fy = F[c][1]; cs.Fz = F[c][2];
+        cs.Gx = G[c][0]; cs.Gy = G[c][1]; cs.Gz = G[c][2];
         T out[Q];
         collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
 #pragma unroll
@@ -574,19 +567,22 @@ hipError_t launch_snapshot(const LaunchCfg& lc, const KParams& kp, const void* g
 
 
 // ------------------------------------------------------------- fused step
-// One launch per step.  The lattice is cut along its slowest axis into
-// planes; XCD k (hardware block b runs on XCD b % 8) owns a contiguous range
-// of planes [P0, P1).  Its workgroups first compute steps 1-5 (densities and
-// ln f) for one 256-node tile of the planes P0-2 .. P1+1 (the two halo planes
-// on each side are recomputed by both neighbouring XCDs, with identical
-// values) and count the tile in a per-plane counter of the XCD; then they run
-// steps 6-9 for a tile 5 planes earlier, after the counters of its planes
-// p-2 .. p+2 are complete.  Every wait is on tiles of lower-numbered blocks of
-// the same XCD, which were dispatched before, so the launch always drains;
-// the waits are also bounded.  The densities and ln f a tile reads were
-// written through the same XCD's L2 (plane sizes are whole 128-byte lines, so
-// no line is read before all of it is written), and the populations are read
-// a second time from the Infinity Cache instead of HBM.
+// One launch per step on a D3Q19 lattice.  XCD k (hardware block b runs on
+// XCD b % 8) owns the y-rows [Y0, Y1) of every plane and sweeps z.  Block j of
+// the XCD computes steps 1-5 (densities and ln f) for tile t = j % tA of
+// A-plane a = j / tA (a = 0 .. nz+3), where A-plane a is plane z = a - 2
+// (wrapped, so planes 0 and 1 are computed again at the end of the sweep)
+// restricted to the rows Y0-2 .. Y1+1 (the two halo rows on each side are
+// recomputed by both neighbouring XCDs; all recomputations give identical
+// values), and counts the tile in the XCD's counter of that A-plane.  It then runs steps 6-9 for tile t of plane
+// z = a - 5 restricted to the rows [Y0, Y1): that needs ln f and densities of
+// A-planes z .. z+4, all complete once A-plane a-1 is, which only lower-
+// numbered blocks of the same XCD compute.  So every wait is on blocks
+// dispatched before, the launch always drains, and the waits are bounded
+// anyway.  The densities and ln f a block reads were written through its own
+// XCD's L2 (rows are whole 128-byte lines, so no line is read before all of it
+// is written); the second read of the populations, 5 band-planes after the
+// first, comes from the Infinity Cache.
 template <int LAT, int NC, typename P, bool MRT>
 __global__ __launch_bounds__(256) void k_fused_step(KParams kp, const P* __restrict__ g, P* __restrict__ gn,
                                                     const float* __restrict__ rref, double* __restrict__ rt,
@@ -600,33 +596,39 @@ __global__ __launch_bounds__(256) void k_fused_step(KParams kp, const P* __restr
         asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
         if ((int)(xcc & 0xf) != k) atomicOr(err, kErrXcd);
     }
-    const int P0 = (int)((long long)k * fc.planes / 8);
-    const int P1 = (int)((long long)(k + 1) * fc.planes / 8);
-    const int np = P1 - P0;
+    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const int Y0 = (int)((long long)k * ny / 8);
+    const int Y1 = (int)((long long)(k + 1) * ny / 8);
+    const int rowsA = Y1 - Y0 + 4, rowsB = Y1 - Y0;
+    const int a = j / fc.tpp;          // A-plane of this block
+    const int t = j - a * fc.tpp;      // tile within the band-plane
+    const int pos = t * 256 + threadIdx.x;
     unsigned* cnt = counters + (size_t)k * fc.cstride;
-    // steps 1-5 for A-tile j
-    if (j < (np + 4) * fc.tpp) {
-        const int al = j / fc.tpp, t = j - al * fc.tpp;
-        int gp = P0 - 2 + al;
-        gp = gp < 0 ? gp + fc.planes : (gp >= fc.planes ? gp - fc.planes : gp);
-        const int off = t * 256 + threadIdx.x;
-        if (off < fc.S && !node_moments_eos<LAT, NC, P>(kp, gp * fc.S + off, kp.N, g, rref, rt, lnf))
-            atomicOr(err, 1);
+    // steps 1-5: tile t of A-plane a
+    if (a < nz + 4) {
+        if (pos < rowsA * nx) {
+            const int rl = pos / nx, x = pos - rl * nx;
+            int y = Y0 - 2 + rl;
+            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            int z = a - 2;
+            z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+            if (!node_moments_eos<LAT, NC, P>(kp, x + nx * (y + ny * z), kp.N, g, rref, rt, lnf))
+                atomicOr(err, kErrDomain);
+        }
         __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the L2
         __syncthreads();
         if (threadIdx.x == 0) {
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __hip_atomic_fetch_add(&cnt[al], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&cnt[a], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    // steps 6-9 for B-tile j - 5 tpp
-    const int jb = j - 5 * fc.tpp;
-    if (jb >= 0 && jb < np * fc.tpp) {
-        const int bl = jb / fc.tpp, t = jb - bl * fc.tpp;
+    // steps 6-9: tile t of plane z = a - 5, rows [Y0, Y1)
+    const int zb = a - 5;
+    if (zb >= 0 && zb < nz) {
         if (threadIdx.x == 0) {
             for (int q = 0; q < 5; ++q) {
                 int spins = 0;
-                while ((int)(__hip_atomic_load(&cnt[bl + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                while ((int)(__hip_atomic_load(&cnt[zb + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                              fc.target) < 0) {
                     if (++spins > fc.spin_limit) {
                         atomicOr(err, kErrWait);
@@ -638,11 +640,11 @@ __global__ __launch_bounds__(256) void k_fused_step(KParams kp, const P* __restr
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
         __syncthreads();
-        const int off = t * 256 + threadIdx.x;
-        if (off < fc.S) {
-            const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
-            node_collide_stream<LAT, NC, P, MRT>(kp, dm, (P0 + bl) * fc.S + off, g, gn, rref, rt, lnf, fsum_in,
-                                                 fsum_out, false);
+        if (pos < rowsB * nx) {
+            const int rl = pos / nx, x = pos - rl * nx;
+            const Dims dm{nx, ny, nz, kp.N};
+            node_collide_stream<LAT, NC, P, MRT>(kp, dm, x + nx * (Y0 + rl + ny * zb), g, gn, rref, rt, lnf,
+                                                 fsum_in, fsum_out, false);
         }
     }
 }
@@ -650,8 +652,7 @@ __global__ __launch_bounds__(256) void k_fused_step(KParams kp, const P* __restr
 hipError_t launch_fused_step(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn, const float* rref,
                              double* rt, double* lnf, const void* fsum_in, void* fsum_out, unsigned* counters,
                              int* err, const FusedCfg& fc) {
-    const int np_max = (fc.planes + 7) / 8;
-    const dim3 grid(8 * (np_max + 5) * fc.tpp);
+    const dim3 grid(8 * (kp.nz + 5) * fc.tpp);
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         if (lc.mrt)

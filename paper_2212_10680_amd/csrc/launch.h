@@ -18,7 +18,7 @@ struct LaunchCfg {
     bool xcd_remap = true;  // XCD-contiguous block order
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
-    bool fused = true;      // one-launch step when the lattice allows it
+    bool fused = false;     // one-launch step (FUGLBM_TUNE fused=1) when the lattice allows it
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
@@ -28,13 +28,11 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
                                  const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                  void* fsum_out);
 
-// Geometry of the fused one-launch step (see k_fused_step).
+// Geometry of the fused one-launch step (see k_fused_step; D3Q19 only).
 struct FusedCfg {
-    int planes;         // planes along the slowest lattice axis
-    int S;              // nodes per plane (multiple of 16)
-    int tpp;            // 256-node tiles per plane
-    int cstride;        // counters per XCD
-    unsigned target;    // counter value of a complete plane in this launch
+    int tpp;            // 256-node tiles of one XCD's band of an A-plane
+    int cstride;        // counters per XCD (>= nz + 2)
+    unsigned target;    // counter value of a complete A-plane in this launch
     int spin_limit;     // bound on every wait loop
 };
 enum { kErrDomain = 1, kErrXcd = 4, kErrWait = 8 };
