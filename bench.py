@@ -47,7 +47,8 @@ def algorithmic_bytes(w, precision):
     """Algorithmic HBM bytes per node of each kernel of one step.
 
     k_moments_eos: read every population, write rho~_i, ln f_i and phi (FP64).
-    k_collide_stream: read and write every population, read rho~_i, ln f_i and
+    k_collide_stream / k_collide_zmarch (the same work; the second stages the
+    FP64 fields through LDS): read and write every population, read rho~_i, ln f_i and
     phi once (the stencil re-reads are cache traffic), read and write the previous
     force sum (D values).  The FP32 form also reads the rest-population reference.
     k_fused_step: the whole step, i.e. the per-node-step figure.
@@ -65,7 +66,8 @@ def algorithmic_bytes(w, precision):
     # ln f and phi once each way, the force history (population precision) once
     # each way, and the FP32 form's rest-population reference once
     step = 2 * pops + 2 * aux + 2 * s * D + ref
-    return {"k_moments_eos": k1, "k_collide_stream": k2, "k_fused_step": step, "step": step}
+    return {"k_moments_eos": k1, "k_collide_stream": k2, "k_collide_zmarch": k2, "k_fused_step": step,
+            "step": step}
 
 
 def stored_traffic(kernel, nodes):

@@ -102,7 +102,8 @@ typedef struct fl_solver fl_solver;
 
 /* Validate params; FL_EINVAL when ncomp is out of range, tau <= 0.5, a Tc, Pc or
  * M <= 0, a kappa < 0, kij not symmetric or with a non-zero diagonal, a
- * lattice dimension < 1 (or nz != 1 for D2Q9), an unknown enum. */
+ * lattice dimension < 1 (or nz != 1 for D2Q9), nx*ny*nz >= 2^29 (every
+ * per-array byte offset stays below 2^32), an unknown enum. */
 int fl_validate(const fl_params* p);
 
 /* Device bytes a solver needs for params (both population buffers, auxiliary

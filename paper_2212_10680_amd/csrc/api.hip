@@ -37,6 +37,7 @@ struct fl_solver {
     int fcur = 0;
     unsigned* counters = nullptr;          // per-XCD plane counters of the fused step
     bool fused = false;                    // one-launch step in use
+    bool zmarch = false;                   // z-marching collide/stream kernel in use
     fl::FusedCfg fc{};
     unsigned fused_launches = 0;
     float* rref = nullptr;
@@ -207,7 +208,12 @@ int setup(fl_solver* s, const fl_params* p) {
         s->fc.target = 0;
         s->fc.spin_limit = 1 << 20;   // about 60 ms of s_sleep per wait
     }
-    // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0"
+    // The collide/stream pass sweeps the nodes in the opposite order to the
+    // moments pass when one population buffer is within a few times the 256 MB
+    // memory-side cache: each pass then starts on the lines the other touched
+    // last.  Larger lattices gain nothing from it.
+    s->lc.reverse_k2 = (double)s->nc * s->Q * s->N * s->pop_elem <= 1073741824.0;
+    // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0,rev=1,zmarch=0,zlen=16"
     if (const char* t = std::getenv("FUGLBM_TUNE")) {
         int v;
         const char* q;
@@ -220,7 +226,12 @@ int setup(fl_solver* s, const fl_params* p) {
         if ((q = std::strstr(t, "serve=")) && std::sscanf(q + 6, "%d", &v) == 1 && (v == 256 || v == 512 || v == 1024))
             s->lc.serve_block = v;
         if ((q = std::strstr(t, "fused=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.fused = v != 0;
+        if ((q = std::strstr(t, "zmarch=")) && std::sscanf(q + 7, "%d", &v) == 1) s->lc.zmarch = v != 0;
+        if ((q = std::strstr(t, "rev=")) && std::sscanf(q + 4, "%d", &v) == 1) s->lc.reverse_k2 = v != 0;
+        if ((q = std::strstr(t, "zlen=")) && std::sscanf(q + 5, "%d", &v) == 1 && v >= 1 && v <= 4096)
+            s->lc.zlen = v;
     }
+    s->zmarch = s->lc.zmarch && fl::zmarch_fits(p->lattice, p->ncomp, p->nx, p->ny);
     return FL_OK;
 }
 
@@ -289,8 +300,12 @@ int one_step(fl_solver* s, hipEvent_t* ev) {
     } else {
         HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
         if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
-        HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
-                                             s->fsum[1 - s->fcur]));
+        if (s->zmarch)
+            HIP_TRY(s, fl::launch_collide_zmarch(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
+                                                 s->fsum[1 - s->fcur]));
+        else
+            HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
+                                                 s->fsum[1 - s->fcur]));
         if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
     }
     s->cur = 1 - s->cur;
@@ -361,8 +376,7 @@ int fl_validate(const fl_params* p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return FL_EINVAL;
     if (D == 2 && p->nz != 1) return FL_EINVAL;
     const double N = (double)p->nx * p->ny * p->nz;
-    if (N * p->ncomp * Q >= 2147483647.0 * 4) return FL_EINVAL;
-    if (N >= 2147483647.0) return FL_EINVAL;
+    if (N >= 536870912.0) return FL_EINVAL;  // 2^29: byte offsets within one array < 2^32
     for (int i = 0; i < p->ncomp; ++i) {
         const fl_component& c = p->comp[i];
         if (!(c.Tc > 0) || !(c.Pc > 0) || !(c.M > 0) || !(c.kappa >= 0) || !std::isfinite(c.omega))
@@ -528,7 +542,7 @@ int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** nam
     } else {
         kernel_ms[0] = acc[0];
         kernel_ms[1] = acc[1];
-        if (names) { names[0] = kNames[0]; names[1] = kNames[1]; }
+        if (names) { names[0] = kNames[0]; names[1] = s->zmarch ? "k_collide_zmarch" : kNames[1]; }
         *nkernels = 2;
     }
     return check_err(s);

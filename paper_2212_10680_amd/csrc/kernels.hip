@@ -18,12 +18,24 @@
 
 namespace fl {
 
+// Element at a 32-bit byte offset from a wave-uniform array base (every
+// per-array byte offset is below 2^32: nodes < 2^29).
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, unsigned byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 template <typename L, int NC, typename P>
 __device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t N, P (&gv)[NC][L::Q]) {
+    const unsigned off = (unsigned)n * (unsigned)sizeof(P);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) gv[c][a] = g[(size_t)(c * L::Q + a) * N + n];
+        for (int a = 0; a < L::Q; ++a) gv[c][a] = ld(g + (size_t)(c * L::Q + a) * N, off);
 }
 
 // rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
@@ -36,25 +48,25 @@ __device__ __forceinline__ void densities(const P (&gv)[NC][L::Q], const float* 
 #pragma unroll
         for (int a = 1; a < L::Q; ++a) m += (double)gv[c][a];
         double r0 = (double)gv[c][0];
-        if constexpr (sizeof(P) == 4) r0 += (double)rref[(size_t)c * N + n];
+        if constexpr (sizeof(P) == 4) r0 += (double)ld(rref + (size_t)c * N, (unsigned)n * 4u);
         moving[c] = m;
         rho[c] = r0 + m;
     }
 }
 
-__device__ __forceinline__ int wrapi(int v, int m) {
-    v %= m;
-    return v < 0 ? v + m : v;
-}
-
-// Node of this thread.  With xcd_chunk > 0 the hardware block b (dispatched
-// round-robin over the 8 XCDs) handles logical block (b % 8) * xcd_chunk + b / 8,
-// so every XCD sweeps one contiguous range of nodes and its L2 keeps the
-// neighbouring planes the stencil needs.
-__device__ __forceinline__ int node_index(int xcd_chunk) {
+// Node of this thread, or -1.  With xcd_chunk > 0 the hardware block b
+// (dispatched round-robin over the 8 XCDs) handles logical block
+// (b % 8) * xcd_chunk + b / 8, so every XCD sweeps one contiguous range of nodes
+// and its L2 keeps the neighbouring planes the stencil needs.  With rev the
+// logical blocks run from the last node to the first: a pass that follows one
+// sweeping the other way starts on the lines that pass touched last, which the
+// memory-side cache still holds.
+__device__ __forceinline__ int node_index(int xcd_chunk, int N, bool rev = false) {
     const int b = blockIdx.x;
-    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
-    return lb * blockDim.x + threadIdx.x;
+    int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    if (rev) lb = (N + (int)blockDim.x - 1) / (int)blockDim.x - 1 - lb;
+    const int n = lb * (int)blockDim.x + (int)threadIdx.x;
+    return (lb < 0 || n >= N) ? -1 : n;
 }
 
 template <typename P>
@@ -102,77 +114,63 @@ __global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __rest
                                                      const float* __restrict__ rref,
                                                      double* __restrict__ rt, double* __restrict__ lnf,
                                                      int* __restrict__ err, int xcd_chunk) {
-    const int n = node_index(xcd_chunk);
-    if (n >= kp.N) return;
+    const int n = node_index(xcd_chunk, kp.N);
+    if (n < 0) return;
     if (!node_moments_eos<LAT, NC, P>(kp, n, kp.N, g, rref, rt, lnf)) atomicOr(err, 1);
 }
 
 // ---------------------------------------------------------------- step 6-9
-// Steps 6-9 (and step 1's velocity) at node n; pushes the collided
-// populations to n + e_a of gn.
-template <int LAT, int NC, typename P, bool MRT>
-__device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dims& dm, int n,
-                                                    const P* __restrict__ g, P* __restrict__ gn,
-                                                    const float* __restrict__ rref,
-                                                    const double* __restrict__ rt,
-                                                    const double* __restrict__ lnf,
-                                                    const P* fsum_in, P* fsum_out, bool nt) {
-    using L = Lat<LAT>;
-    constexpr int D = L::D, Q = L::Q;
-    using T = P;  // collision precision
-    const size_t N = dm.N;
-    const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
-    const int x = n % nx;
-    const int t = n / nx;
-    const int y = t % ny;
-    const int z = t / ny;
-    int X[5], Y[5], Z[5];
-#pragma unroll
-    for (int d = -2; d <= 2; ++d) {
-        X[d + 2] = wrapi(x + d, nx);
-        Y[d + 2] = wrapi(y + d, ny);
-        Z[d + 2] = (D == 3) ? wrapi(z + d, nz) : 0;
-    }
-    auto idx = [&](int dx, int dy, int dz) { return X[dx + 2] + nx * (Y[dy + 2] + ny * Z[dz + 2]); };
-    auto unit = [](int k, int s, int& dx, int& dy, int& dz) {
-        dx = (k == 0) ? s : 0;
-        dy = (k == 1) ? s : 0;
-        dz = (k == 2) ? s : 0;
-    };
+// wrap v into [0, m) for |v - [0, m)| <= 2m (stencil offsets of at most 2)
+__device__ __forceinline__ int wrap2(int v, int m) {
+    v = v < 0 ? v + m : v;
+    v = v < 0 ? v + m : v;
+    v = v >= m ? v - m : v;
+    return v >= m ? v - m : v;
+}
 
-    // step 6: interface potential.  With kappa_ij = sqrt(kappa_i kappa_j)
-    // (eqkappa), mu_I,i = -sum_j kappa_ij lap(rho~_j) = -sqrt(kappa_i) lap(phi)
-    // with phi = sum_j sqrt(kappa_j) rho~_j, written by the moments pass: one
-    // scalar Laplacian (eq2ndder per axis) at each of the 2D neighbours.
-    const double* phi = lnf + (size_t)NC * N;
+__device__ __forceinline__ void unit_offset(int k, int s, int& dx, int& dy, int& dz) {
+    dx = (k == 0) ? s : 0;
+    dy = (k == 1) ? s : 0;
+    dz = (k == 2) ? s : 0;
+}
+
+// Steps 6-7 at one node from accessors of the FP64 fields of the moments pass:
+// phi_at(dx,dy,dz) (Manhattan radius 2), rt_at(i,dx,dy,dz) and
+// lnf_at(i,dx,dy,dz) (radius 1).  Every offset is a compile-time constant after
+// unrolling, so an accessor resolves to one global, LDS or register read.
+//   step 6: with kappa_ij = sqrt(kappa_i kappa_j) (eqkappa),
+//     mu_I,i = -sum_j kappa_ij lap(rho~_j) = -sqrt(kappa_i) lap(phi),
+//     phi = sum_j sqrt(kappa_j) rho~_j: one scalar Laplacian (eq2ndder per
+//     axis) at each of the 2D neighbours;
+//   step 7: F_i = -rho~_i [RT D(ln f_i) + D(mu_I,i)] and grad rho_i by central
+//     differences (eq1stder).
+// F and G are evaluated in FP64 and kept in the collision precision T (the
+// collision reads them there); their sum over components stays FP64.
+template <int D, int NC, typename T, class PhiAt, class RtAt, class LnfAt>
+__device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at, RtAt&& rt_at, LnfAt&& lnf_at,
+                                              T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
     double mh[2 * D];  // -lap(phi) at n + e_k (index 2k) and n - e_k (index 2k+1)
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             int cx, cy, cz;
-            unit(k, s == 0 ? 1 : -1, cx, cy, cz);
-            const double p0 = phi[idx(cx, cy, cz)];
+            unit_offset(k, s == 0 ? 1 : -1, cx, cy, cz);
+            const double p0 = phi_at(cx, cy, cz);
             double acc = 0.0;
 #pragma unroll
             for (int m = 0; m < D; ++m) {
                 int mx, my, mz;
-                unit(m, 1, mx, my, mz);
-                acc += phi[idx(cx + mx, cy + my, cz + mz)] - 2.0 * p0 + phi[idx(cx - mx, cy - my, cz - mz)];
+                unit_offset(m, 1, mx, my, mz);
+                acc += phi_at(cx + mx, cy + my, cz + mz) - 2.0 * p0 + phi_at(cx - mx, cy - my, cz - mz);
             }
             mh[2 * k + s] = -acc;
         }
-
-    // step 7: F_i = -rho~_i [RT D(ln f_i) + D(mu_I,i)] (eq1stder), and grad rho_i.
-    // Evaluated in FP64, kept in the collision precision (the collision reads
-    // them there); their sum over components stays FP64.
-    T F[NC][3], G[NC][3];
-    double Fs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-        const double* lf = lnf + (size_t)i * N;
-        const double* r = rt + (size_t)i * N;
-        const double rc = r[n];
+        const double rc = rt_at(i, 0, 0, 0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             F[i][k] = T(0);
@@ -181,20 +179,58 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             int px, py, pz;
-            unit(k, 1, px, py, pz);
-            const int ip = idx(px, py, pz), im = idx(-px, -py, -pz);
-            const double dl = (lf[ip] - lf[im]) / 2.0;
+            unit_offset(k, 1, px, py, pz);
+            const double dl = (lnf_at(i, px, py, pz) - lnf_at(i, -px, -py, -pz)) / 2.0;
             const double dm = kp.sk[i] * (mh[2 * k] - mh[2 * k + 1]) / 2.0;
             const double f = -rc * (kp.RT * dl + dm);
             Fs[k] += f;
             F[i][k] = T(f);
-            G[i][k] = T(kp.M[i] * (r[ip] - r[im]) / 2.0);
+            G[i][k] = T(kp.M[i] * (rt_at(i, px, py, pz) - rt_at(i, -px, -py, -pz)) / 2.0);
         }
     }
+}
 
-    // step 1 (again, for this node): moments and velocity
+// Steps 8-9 (and step 1's velocity) at node n = (x, y, z): moments of the
+// node's populations, u with the force of the chosen time level, equilibrium,
+// forcing and collision per component, push streaming to n + e_a of gn.
+// With NTLD the node's populations are loaded with the non-temporal hint: each
+// is read once per pass, and keeping them out of the way leaves L2 to the FP64
+// stencil fields that neighbouring nodes re-read.
+template <int LAT, int NC, typename P, bool MRT, bool NTLD = false>
+__device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, int n, int x, int y, int z,
+                                             const P* __restrict__ g, P* __restrict__ gn,
+                                             const float* __restrict__ rref, const P (&F)[NC][3],
+                                             const P (&G)[NC][3], const double (&Fs)[3], const P* fsum_in,
+                                             P* fsum_out, bool nt) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    using T = P;  // collision precision
+    const size_t N = dm.N;
+    // periodic neighbour n + e_a as n plus per-axis steps (wrapped at the faces)
+    const int nx = dm.nx, sy = dm.nx, sz = dm.nx * dm.ny;
+    const int step[3][2] = {{x == 0 ? nx - 1 : -1, x == nx - 1 ? 1 - nx : 1},
+                            {y == 0 ? (dm.ny - 1) * sy : -sy, y == dm.ny - 1 ? (1 - dm.ny) * sy : sy},
+                            {z == 0 ? (dm.nz - 1) * sz : -sz, z == dm.nz - 1 ? (1 - dm.nz) * sz : sz}};
+    auto nbr_off = [&](int dx, int dy, int dz) {
+        int m = n;
+        if (dx) m += step[0][dx > 0];
+        if (dy) m += step[1][dy > 0];
+        if (D == 3 && dz) m += step[2][dz > 0];
+        return (unsigned)m * (unsigned)sizeof(P);
+    };
+
     P gv[NC][Q];
-    load_pops<L, NC, P>(g, n, N, gv);
+    if constexpr (NTLD) {
+        const unsigned off = (unsigned)n * (unsigned)sizeof(P);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int a = 0; a < Q; ++a)
+                gv[c][a] = __builtin_nontemporal_load(
+                    reinterpret_cast<const P*>(reinterpret_cast<const char*>(g + (size_t)(c * Q + a) * N) + off));
+    } else {
+        load_pops<L, NC, P>(g, n, N, gv);
+    }
     double rho[NC], mov[NC];
     densities<L, NC, P>(gv, rref, n, N, rho, mov);
     double rtot = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -211,11 +247,9 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : (double)fsum_in[(size_t)k * N + n];
+        const double fk = kp.force_level ? Fs[k] : (double)ld(fsum_in + (size_t)k * N, (unsigned)n * (unsigned)sizeof(P));
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
-
-    // steps 8-9 per component, push streaming into the other buffer
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         CompState<T> cs;
@@ -227,10 +261,51 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
         collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
-            store_pop(&gn[(size_t)(c * Q + a) * N + idx(L::ex[a], L::ey[a], L::ez[a])], out[a], nt);
+        {
+            P* dst = gn + (size_t)(c * Q + a) * N;
+            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]);
+            if (nt)
+                __builtin_nontemporal_store(out[a], (P*)((char*)dst + off));
+            else
+                st(dst, off, out[a]);
+        }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) fsum_out[(size_t)k * N + n] = (P)Fs[k];
+    for (int k = 0; k < D; ++k) st(fsum_out + (size_t)k * N, (unsigned)n * (unsigned)sizeof(P), (P)Fs[k]);
+}
+
+// Steps 6-9 at node n reading the FP64 fields straight from global memory.
+template <int LAT, int NC, typename P, bool MRT, bool NTLD = false>
+__device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dims& dm, int n,
+                                                    const P* __restrict__ g, P* __restrict__ gn,
+                                                    const float* __restrict__ rref,
+                                                    const double* __restrict__ rt,
+                                                    const double* __restrict__ lnf,
+                                                    const P* fsum_in, P* fsum_out, bool nt) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const size_t N = dm.N;
+    const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
+    const int x = n % nx;
+    const int t = n / nx;
+    const int y = t % ny;
+    const int z = t / ny;
+    int X[5], Y[5], Z[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        X[d + 2] = wrap2(x + d, nx);
+        Y[d + 2] = wrap2(y + d, ny);
+        Z[d + 2] = (D == 3) ? wrap2(z + d, nz) : 0;
+    }
+    auto idx = [&](int dx, int dy, int dz) { return X[dx + 2] + nx * (Y[dy + 2] + ny * Z[dz + 2]); };
+    const double* phi = lnf + (size_t)NC * N;
+    P F[NC][3], G[NC][3];
+    double Fs[3];
+    stencil_force<D, NC, P>(
+        kp, [&](int dx, int dy, int dz) { return phi[idx(dx, dy, dz)]; },
+        [&](int i, int dx, int dy, int dz) { return rt[(size_t)i * N + idx(dx, dy, dz)]; },
+        [&](int i, int dx, int dy, int dz) { return lnf[(size_t)i * N + idx(dx, dy, dz)]; }, F, G, Fs);
+    collide_push<LAT, NC, P, MRT, NTLD>(kp, dm, n, x, y, z, g, gn, rref, F, G, Fs, fsum_in, fsum_out, nt);
 }
 
 template <int LAT, int NC, typename P, bool MRT>
@@ -239,11 +314,160 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
                                                         const float* __restrict__ rref,
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
-                                                        const P* fsum_in, P* fsum_out, int xcd_chunk, int nt) {
-    const int n = node_index(xcd_chunk);
-    if (n >= kp.N) return;
+                                                        const P* fsum_in, P* fsum_out, int xcd_chunk, int nt,
+                                                        int rev) {
+    const int n = node_index(xcd_chunk, kp.N, rev != 0);
+    if (n < 0) return;
     const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
-    node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
+    node_collide_stream<LAT, NC, P, MRT, true>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
+}
+
+// ------------------------------------------------ steps 6-9, z-marching form
+// D3Q19.  A 256-thread workgroup owns a kZX x kZY tile of (x, y) and sweeps the
+// planes z0 .. z1-1 of its z-range.  The FP64 fields of the moments pass are
+// staged through LDS so that each is read from memory about once per step
+// instead of once per stencil point:
+//   phi        planes z-1, z, z+1 (tile + halo 2) in a ring of 4 slots, while
+//              plane z+2 is loaded into the fourth;
+//   rt, ln f   plane z (tile + halo 1) in a ring of 2 slots, while plane z+1 is
+//              loaded into the other;
+// the node's own column supplies phi(z-2) and rt, ln f(z-1) from registers
+// (values of earlier planes) and phi(z+2), rt, ln f(z+1) from the lines the
+// fill of those planes is bringing into the caches.  The per-node arithmetic is
+// stencil_force + collide_push, as in k_collide_stream.
+constexpr int kZX = 64, kZY = 4;
+constexpr int kPhiW = kZX + 4, kPhiH = kZY + 4;  // phi tile + halo 2
+constexpr int kRlW = kZX + 2, kRlH = kZY + 2;    // rt / ln f tile + halo 1
+constexpr int kPhiPts = kPhiW * kPhiH;
+constexpr int kRlPts = kRlW * kRlH;
+constexpr int kPhiPer = (kPhiPts + 255) / 256;   // fill points per thread
+constexpr int kRlPer = (kRlPts + 255) / 256;
+
+template <int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __restrict__ g,
+                                                        P* __restrict__ gn,
+                                                        const float* __restrict__ rref,
+                                                        const double* __restrict__ rt,
+                                                        const double* __restrict__ lnf,
+                                                        const P* fsum_in, P* fsum_out, int zlen, int xcd_chunk,
+                                                        int nt) {
+    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const size_t N = kp.N;
+    const int plane = nx * ny;
+    const int tiles_x = nx / kZX;
+    const int tiles_xy = tiles_x * (ny / kZY);
+    const int nzc = (nz + zlen - 1) / zlen;
+    const int b = blockIdx.x;
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
+    const int zc = lb / tiles_xy, txy = lb - zc * tiles_xy;
+    const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
+    const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
+    const int t = threadIdx.x;
+    const int tx = t % kZX, ty = t / kZX;
+    const int x = x0 + tx, y = y0 + ty;
+    const int col = x + nx * y;
+    const Dims dm{nx, ny, nz, kp.N};
+    const double* phig = lnf + (size_t)NC * N;
+
+    __shared__ double s_phi[4][kPhiPts];
+    __shared__ double s_rl[2][2 * NC][kRlPts];  // rt_i, then ln f_i
+
+    // fill pattern, the same for every plane: byte offset of each point in its
+    // plane (points past the tile read offset 0 and are not stored)
+    unsigned phi_off[kPhiPer], rl_off[kRlPer];
+#pragma unroll
+    for (int k = 0; k < kPhiPer; ++k) {
+        const int p = t + 256 * k;
+        phi_off[k] = p < kPhiPts ? 8u * (unsigned)(wrap2(x0 - 2 + p % kPhiW, nx) + nx * wrap2(y0 - 2 + p / kPhiW, ny)) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kRlPer; ++k) {
+        const int p = t + 256 * k;
+        rl_off[k] = p < kRlPts ? 8u * (unsigned)(wrap2(x0 - 1 + p % kRlW, nx) + nx * wrap2(y0 - 1 + p / kRlW, ny)) : 0u;
+    }
+    // only the last fill row can run past the tile
+    auto phi_fills = [&](int k) { return k < kPhiPer - 1 || t + 256 * k < kPhiPts; };
+    auto rl_fills = [&](int k) { return k < kRlPer - 1 || t + 256 * k < kRlPts; };
+    auto zoff = [&](int zz) { return (size_t)wrap2(zz, nz) * plane; };
+    auto rl_src = [&](int f) { return f < NC ? rt + (size_t)f * N : lnf + (size_t)(f - NC) * N; };
+    const unsigned col8 = 8u * (unsigned)col;
+
+    // prologue: phi planes z0-1, z0, z0+1 -> slots 0, 1, 2; rt/ln f plane z0 -> slot 0
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double* src = phig + zoff(z0 - 1 + d);
+#pragma unroll
+        for (int k = 0; k < kPhiPer; ++k)
+            if (phi_fills(k)) s_phi[d][t + 256 * k] = ld(src, phi_off[k]);
+    }
+#pragma unroll
+    for (int f = 0; f < 2 * NC; ++f) {
+        const double* src = rl_src(f) + zoff(z0);
+#pragma unroll
+        for (int k = 0; k < kRlPer; ++k)
+            if (rl_fills(k)) s_rl[0][f][t + 256 * k] = ld(src, rl_off[k]);
+    }
+    double phi_m2 = ld(phig + zoff(z0 - 2), col8);
+    double phi_m1 = ld(phig + zoff(z0 - 1), col8);
+    double rl_m1[2 * NC];
+#pragma unroll
+    for (int f = 0; f < 2 * NC; ++f) rl_m1[f] = ld(rl_src(f) + zoff(z0 - 1), col8);
+    __syncthreads();
+
+    const int cphi = (ty + 2) * kPhiW + tx + 2;  // this node in the phi tile
+    const int crl = (ty + 1) * kRlW + tx + 1;    // this node in the rt / ln f tile
+    for (int zz = z0, it = 0; zz < z1; ++zz, ++it) {
+        // loads of the planes being filled (written to LDS after the node's work)
+        double fphi[kPhiPer], frl[2 * NC][kRlPer];
+        const double* phi2 = phig + zoff(zz + 2);
+#pragma unroll
+        for (int k = 0; k < kPhiPer; ++k) fphi[k] = ld(phi2, phi_off[k]);
+        const size_t z1off = zoff(zz + 1);
+#pragma unroll
+        for (int f = 0; f < 2 * NC; ++f)
+#pragma unroll
+            for (int k = 0; k < kRlPer; ++k) frl[f][k] = ld(rl_src(f) + z1off, rl_off[k]);
+        const double phi_p2 = ld(phi2, col8);
+        double rl_p1[2 * NC];
+#pragma unroll
+        for (int f = 0; f < 2 * NC; ++f) rl_p1[f] = ld(rl_src(f) + z1off, col8);
+
+        const int s0 = (it + 1) & 3;  // phi slot of plane zz (plane z0-1+j lives in slot j&3)
+        const int r0 = it & 1;        // rt / ln f slot of plane zz
+        auto phi_at = [&](int dx, int dy, int dz) -> double {
+            if (dz == -2) return phi_m2;
+            if (dz == 2) return phi_p2;
+            return s_phi[(s0 + dz) & 3][cphi + dy * kPhiW + dx];
+        };
+        auto rl_at = [&](int f, int dx, int dy, int dz) -> double {
+            if (dz == -1) return rl_m1[f];
+            if (dz == 1) return rl_p1[f];
+            return s_rl[r0][f][crl + dy * kRlW + dx];
+        };
+        P F[NC][3], G[NC][3];
+        double Fs[3];
+        stencil_force<3, NC, P>(
+            kp, phi_at, [&](int i, int dx, int dy, int dz) { return rl_at(i, dx, dy, dz); },
+            [&](int i, int dx, int dy, int dz) { return rl_at(NC + i, dx, dy, dz); }, F, G, Fs);
+        collide_push<1, NC, P, MRT, true>(kp, dm, col + zz * plane, x, y, zz, g, gn, rref, F, G, Fs, fsum_in,
+                                          fsum_out, nt != 0);
+
+        // shift the own-column registers, store the filled planes, publish
+        phi_m2 = phi_m1;
+        phi_m1 = s_phi[s0][cphi];
+#pragma unroll
+        for (int f = 0; f < 2 * NC; ++f) rl_m1[f] = s_rl[r0][f][crl];
+#pragma unroll
+        for (int k = 0; k < kPhiPer; ++k)
+            if (phi_fills(k)) s_phi[(it + 3) & 3][t + 256 * k] = fphi[k];
+#pragma unroll
+        for (int f = 0; f < 2 * NC; ++f)
+#pragma unroll
+            for (int k = 0; k < kRlPer; ++k)
+                if (rl_fills(k)) s_rl[(it + 1) & 1][f][t + 256 * k] = frl[f][k];
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------ initial state
@@ -487,14 +711,40 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
     const int nb = (kp.N + bs - 1) / bs;
     const int ch = xcd_chunk_for(lc, nb);
     const int nt = lc.nt_store ? 1 : 0;
+    const int rev = lc.reverse_k2 ? 1 : 0;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         if (lc.mrt)
             k_collide_stream<LAT, NC, P, true><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev);
         else
             k_collide_stream<LAT, NC, P, false><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev);
+    });
+    return hipGetLastError();
+}
+
+bool zmarch_fits(int lattice, int nc, int nx, int ny) {
+    return lattice == 1 && nc <= 3 && nx % kZX == 0 && ny % kZY == 0;
+}
+
+hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                 const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                 void* fsum_out) {
+    if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1) return hipErrorInvalidValue;
+    const int nb = (kp.nx / kZX) * (kp.ny / kZY) * ((kp.nz + lc.zlen - 1) / lc.zlen);
+    const int ch = xcd_chunk_for(lc, nb);
+    const int nt = lc.nt_store ? 1 : 0;
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        if constexpr (LAT == 1 && NC <= 3) {
+            if (lc.mrt)
+                k_collide_zmarch<NC, P, true><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+            else
+                k_collide_zmarch<NC, P, false><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+        }
     });
     return hipGetLastError();
 }

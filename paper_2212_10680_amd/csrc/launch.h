@@ -19,6 +19,9 @@ struct LaunchCfg {
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
     bool fused = false;     // one-launch step (FUGLBM_TUNE fused=1) when the lattice allows it
+    bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (FUGLBM_TUNE zmarch=1)
+    bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
+    int zlen = 16;          // planes per workgroup of the z-marching kernel
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
@@ -40,6 +43,12 @@ hipError_t launch_fused_step(const LaunchCfg& lc, const KParams& kp, const void*
                              double* rt, double* lnf, const void* fsum_in, void* fsum_out, unsigned* counters,
                              int* err, const FusedCfg& fc);
 hipError_t launch_xcd_ids(int* out, int nblocks, hipStream_t stream);
+// z-marching form of launch_collide_stream: D3Q19, N_c <= 3, nx % 64 == 0,
+// ny % 4 == 0 (zmarch_fits); hipErrorInvalidValue otherwise.
+bool zmarch_fits(int lattice, int nc, int nx, int ny);
+hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                 const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                 void* fsum_out);
 hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
                        void* g, float* rref, void* fsum);
 hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,

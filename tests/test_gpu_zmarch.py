@@ -1,0 +1,142 @@
+"""The z-marching collide/stream kernel (k_collide_zmarch) against the plain
+one (k_collide_stream) and the oracle.
+
+Both kernels run the same per-node expressions (stencil_force +
+collide_push) and differ only in where the stencil values come from (LDS
+rings and registers vs global memory), so they must agree bitwise; a wrong
+slot, halo offset or register shift changes bits.  Shapes cover several
+tiles in x and y, z-ranges that do not divide nz, a single plane, FP64 and
+FP32 populations, BGK and MRT, and the two benchmark lattices.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2212_10680_amd import fuglbm as F
+from paper_2212_10680_amd import workloads as wl
+
+from _util import direction_map, oracle_for, rel, smooth_3d_field
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def solver(w, precision, tune):
+    old = os.environ.get("FUGLBM_TUNE")
+    os.environ["FUGLBM_TUNE"] = tune
+    try:
+        s = F.Solver(F.Params.from_workload(w, precision=precision))
+    finally:
+        if old is None:
+            del os.environ["FUGLBM_TUNE"]
+        else:
+            os.environ["FUGLBM_TUNE"] = old
+    return s
+
+
+CASES = [
+    ("binary_slab_3d", (64, 8, 5), "fp64", "BGK", 2),      # ragged last z-range
+    ("binary_slab_3d", (128, 8, 9), "fp32", "BGK", 4),
+    ("ternary_droplets_3d", (64, 12, 16), "fp32", "MRT", 16),
+    ("ternary_droplets_3d", (64, 4, 7), "fp64", "MRT", 3),
+    ("binary_slab_3d", (192, 8, 6), "fp32", "MRT", 5),
+    ("binary_slab_3d", (64, 4, 1), "fp64", "BGK", 16),     # one plane
+]
+
+
+@pytest.mark.parametrize("wname,shape,precision,coll,zlen", CASES)
+def test_zmarch_equals_plain_bitwise(wname, shape, precision, coll, zlen):
+    w = wl.WORKLOADS[wname].scaled(shape)
+    w.collision = coll
+    w.u0 = 0.0
+    if w.geometry == "two_droplets":
+        w.geometry = "slab"
+    announce(f"zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen}")
+    rho, u = smooth_3d_field(w, amp=0.005)
+    a = solver(w, precision, f"zmarch=1,zlen={zlen}")
+    b = solver(w, precision, "zmarch=0")
+    a.set_state(rho, u)
+    b.set_state(rho, u)
+    assert list(a.step_timed(2)) == ["k_moments_eos", "k_collide_zmarch"]
+    assert list(b.step_timed(2)) == ["k_moments_eos", "k_collide_stream"]
+    a.step(18)
+    b.step(18)
+    ga, gb = a.populations(), b.populations()
+    print(f"  max |diff| {np.max(np.abs(ga - gb)):.3e}", flush=True)
+    assert np.array_equal(ga, gb)
+    assert np.array_equal(a.fields()["u"], b.fields()["u"])
+
+
+def test_zmarch_fp64_vs_oracle():
+    w = wl.WORKLOADS["ternary_droplets_3d"].scaled((64, 8, 6))
+    w.geometry = "slab"
+    w.u0 = 0.0
+    w.precision = "fp64"
+    announce("zmarch FP64 vs oracle")
+    rho, u = smooth_3d_field(w)
+    o = oracle_for(w)
+    o.init(rho.reshape(3, -1))
+    s = solver(w, "fp64", "zmarch=1,zlen=4")
+    s.set_state(rho)
+    assert list(s.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch"]
+    o.run(1)
+    s.step(9)
+    o.run(9)
+    e, _ = F.lattice_table(w.lattice)
+    err = rel(s.populations(), o.g[:, direction_map(w.lattice, e), :])
+    er = rel(s.fields()["rho_molar"], o.fields()["rho_molar"])
+    print(f"  pops {err:.2e} rho {er:.2e}", flush=True)
+    assert err < 1e-12 and er < 1e-12
+
+
+@pytest.mark.parametrize("wname", ["binary_slab_3d", "ternary_droplets_3d"])
+def test_bench_lattices_zmarch_equals_plain(wname):
+    """The benchmark lattices at full size (D3Q19 128^3 binary BGK and 256^3
+    ternary MRT, FP32 populations): the z-marching kernel bitwise equal to the
+    plain one (default launch configuration) after a few steps."""
+    w = wl.WORKLOADS[wname]
+    announce(f"bench lattice {wname} {w.shape}")
+    rho, u = wl.initial_field(w)
+    steps = 6 if w.shape[0] <= 128 else 3
+    a = solver(w, "fp32", "zmarch=1")
+    a.set_state(rho, u)
+    assert list(a.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch"]
+    a.step(steps - 1)
+    fa = a.fields()["rho_molar"]
+    a.close()
+    del a
+    b = solver(w, "fp32", "")
+    b.set_state(rho, u)
+    assert list(b.step_timed(1)) == ["k_moments_eos", "k_collide_stream"]
+    b.step(steps - 1)
+    assert np.array_equal(fa, b.fields()["rho_molar"])
+
+
+@pytest.mark.parametrize("wname,shape,precision,coll", [
+    ("binary_slab_3d", (64, 8, 5), "fp32", "BGK"),
+    ("ternary_droplets_3d", (24, 12, 7), "fp64", "MRT"),
+])
+def test_sweep_order_bitwise(wname, shape, precision, coll):
+    """The order in which the collide/stream pass visits the nodes (forward or
+    reversed, XCD-contiguous or plain block order) changes no bit."""
+    w = wl.WORKLOADS[wname].scaled(shape)
+    w.collision = coll
+    w.u0 = 0.0
+    if w.geometry == "two_droplets":
+        w.geometry = "slab"
+    announce(f"sweep order {wname} {shape} {precision} {coll}")
+    rho, u = smooth_3d_field(w, amp=0.005)
+    ref = None
+    for tune in ("rev=0,remap=1", "rev=1,remap=1", "rev=1,remap=0", "rev=0,remap=0"):
+        s = solver(w, precision, tune)
+        s.set_state(rho, u)
+        s.step(15)
+        g = s.populations()
+        s.close()
+        if ref is None:
+            ref = g
+        assert np.array_equal(g, ref), tune

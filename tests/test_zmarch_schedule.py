@@ -1,0 +1,149 @@
+"""CPU replay of the z-marching collide/stream kernel's data staging.
+
+The kernel (k_collide_zmarch) gives each 256-thread workgroup a 64 x 4 tile of
+(x, y) and a range of z planes, keeps phi in a 4-slot LDS ring (tile + halo 2),
+rt and ln f in a 2-slot ring (tile + halo 1), and the node's own column at
+z +- 1, z +- 2 in registers or fresh loads.  This replays that schedule with
+the kernel's index arithmetic (fill offsets, slot numbers, register shifts,
+block order over the XCDs) and checks, for every node of every plane, that
+each value the stencil reads is the field at the periodic neighbour the
+stencil means, and that every LDS and global index stays inside its buffer.
+"""
+import numpy as np
+import pytest
+
+ZX, ZY = 64, 4
+PHI_W, PHI_H = ZX + 4, ZY + 4
+RL_W, RL_H = ZX + 2, ZY + 2
+PHI_PTS, RL_PTS = PHI_W * PHI_H, RL_W * RL_H
+PHI_PER, RL_PER = (PHI_PTS + 255) // 256, (RL_PTS + 255) // 256
+
+PHI_OFFS = [(dx, dy, dz) for dx in range(-2, 3) for dy in range(-2, 3) for dz in range(-2, 3)
+            if abs(dx) + abs(dy) + abs(dz) <= 2]
+RL_OFFS = [(0, 0, 0)] + [tuple(s * (k == m) for m in range(3)) for k in range(3) for s in (1, -1)]
+
+
+def wrap2(v, m):
+    v = np.where(v < 0, v + m, v)
+    v = np.where(v < 0, v + m, v)
+    v = np.where(v >= m, v - m, v)
+    return np.where(v >= m, v - m, v)
+
+
+def replay(nx, ny, nz, zlen, remap=True):
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    phi = rng.standard_normal((nz, ny, nx))
+    rl = rng.standard_normal((nz, ny, nx))   # one rt / ln f field stands for all
+    plane = nx * ny
+    tiles_x = nx // ZX
+    tiles_xy = tiles_x * (ny // ZY)
+    nzc = (nz + zlen - 1) // zlen
+    nb = tiles_xy * nzc
+    chunk = (nb + 7) // 8 if remap else 0
+    grid = 8 * chunk if remap else nb
+    seen = []
+    flat_phi, flat_rl = phi.reshape(-1), rl.reshape(-1)
+    t = np.arange(256)
+    tx, ty = t % ZX, t // ZX
+    visits = np.zeros((nz, ny, nx), dtype=int)
+    for b in range(grid):
+        lb = (b & 7) * chunk + (b >> 3) if remap else b
+        if lb >= nb:
+            continue
+        seen.append(lb)
+        zc, txy = lb // tiles_xy, lb % tiles_xy
+        x0, y0 = (txy % tiles_x) * ZX, (txy // tiles_x) * ZY
+        z0, z1 = zc * zlen, min(zc * zlen + zlen, nz)
+        x, y = x0 + tx, y0 + ty
+        col = x + nx * y
+        phi_off, rl_off = [], []
+        for k in range(PHI_PER):
+            p = t + 256 * k
+            phi_off.append(np.where(p < PHI_PTS, wrap2(x0 - 2 + p % PHI_W, nx) + nx * wrap2(y0 - 2 + p // PHI_W, ny), -1))
+        for k in range(RL_PER):
+            p = t + 256 * k
+            rl_off.append(np.where(p < RL_PTS, wrap2(x0 - 1 + p % RL_W, nx) + nx * wrap2(y0 - 1 + p // RL_W, ny), -1))
+        for o in phi_off + rl_off:
+            assert np.all((o == -1) | ((o >= 0) & (o < plane)))
+
+        def zoff(zz):
+            z = int(wrap2(np.array(zz), nz))
+            assert 0 <= z < nz
+            return z * plane
+
+        s_phi = np.full((4, PHI_PTS), np.nan)
+        s_rl = np.full((2, RL_PTS), np.nan)
+
+        def fill(dst, slot, src, offs):
+            for k, o in enumerate(offs):
+                m = o >= 0
+                idx = (t + 256 * k)[m]
+                assert idx.max() < dst.shape[1]
+                dst[slot, idx] = src[o[m]]
+
+        for d in range(3):
+            fill(s_phi, d, flat_phi[zoff(z0 - 1 + d):], phi_off)
+        fill(s_rl, 0, flat_rl[zoff(z0):], rl_off)
+        phi_m2 = flat_phi[zoff(z0 - 2) + col]
+        phi_m1 = flat_phi[zoff(z0 - 1) + col]
+        rl_m1 = flat_rl[zoff(z0 - 1) + col]
+        cphi = (ty + 2) * PHI_W + tx + 2
+        crl = (ty + 1) * RL_W + tx + 1
+        for it, zz in enumerate(range(z0, z1)):
+            fphi = [np.where(o >= 0, flat_phi[zoff(zz + 2) + np.maximum(o, 0)], 0.0) for o in phi_off]
+            frl = [np.where(o >= 0, flat_rl[zoff(zz + 1) + np.maximum(o, 0)], 0.0) for o in rl_off]
+            phi_p2 = flat_phi[zoff(zz + 2) + col]
+            rl_p1 = flat_rl[zoff(zz + 1) + col]
+            s0, r0 = (it + 1) & 3, it & 1
+            for dx, dy, dz in PHI_OFFS:
+                if dz == -2:
+                    got = phi_m2
+                elif dz == 2:
+                    got = phi_p2
+                else:
+                    i = cphi + dy * PHI_W + dx
+                    assert i.min() >= 0 and i.max() < PHI_PTS
+                    got = s_phi[(s0 + dz) & 3, i]
+                want = phi[wrap2(zz + dz, nz), wrap2(y + dy, ny), wrap2(x + dx, nx)]
+                np.testing.assert_array_equal(got, want, err_msg=f"phi {dx, dy, dz} z={zz}")
+            for dx, dy, dz in RL_OFFS:
+                if dz == -1:
+                    got = rl_m1
+                elif dz == 1:
+                    got = rl_p1
+                else:
+                    i = crl + dy * RL_W + dx
+                    assert i.min() >= 0 and i.max() < RL_PTS
+                    got = s_rl[r0, i]
+                want = rl[wrap2(zz + dz, nz), wrap2(y + dy, ny), wrap2(x + dx, nx)]
+                np.testing.assert_array_equal(got, want, err_msg=f"rl {dx, dy, dz} z={zz}")
+            n = col + zz * plane
+            assert n.min() >= 0 and n.max() < plane * nz
+            visits[zz, y, x] += 1
+            phi_m2, phi_m1 = phi_m1, s_phi[s0, cphi]
+            rl_m1 = s_rl[r0, crl]
+            for k in range(PHI_PER):
+                m = phi_off[k] >= 0
+                s_phi[(it + 3) & 3, (t + 256 * k)[m]] = fphi[k][m]
+            for k in range(RL_PER):
+                m = rl_off[k] >= 0
+                s_rl[(it + 1) & 1, (t + 256 * k)[m]] = frl[k][m]
+    assert sorted(seen) == list(range(nb))
+    assert np.all(visits == 1)
+
+
+@pytest.mark.parametrize("nx,ny,nz,zlen", [
+    (64, 4, 1, 16),     # one plane: every z neighbour is the plane itself
+    (64, 4, 2, 16),
+    (64, 8, 5, 2),      # ragged last z-range
+    (128, 8, 9, 4),
+    (64, 12, 16, 16),   # three tile rows, one z-range
+    (128, 4, 7, 3),
+    (192, 8, 6, 5),
+])
+def test_zmarch_schedule(nx, ny, nz, zlen):
+    replay(nx, ny, nz, zlen)
+
+
+def test_zmarch_schedule_no_remap():
+    replay(64, 8, 6, 4, remap=False)
