@@ -120,7 +120,7 @@ def cpu_baseline(w, budget_s=15.0):
 
 
 def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, plain_subset=16,
-                  tol=1e-10, check_every=1000):
+                  tol=1e-10, check_every=1000, accuracy_subset=8):
     """Batched VLE serving: FP32-population server vs the plain FP64 path.
 
     Requests: binary D2Q9 L x 8 slabs, L log-uniform in [64, 2048], feed z1
@@ -143,11 +143,14 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, pl
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
     batched = {}
     opened = serving.serve(srv, reqs, arrivals, tol, check_every, max_steps, tick_ms,
-                           on_result=lambda rec, rho: batched.__setitem__(rec["i"], (rho, rec["steps"])))
+                           on_result=lambda rec, rho: batched.__setitem__(rec["i"], (rho, rec["steps"], rec["status"])))
     srv.close()
     print(f"[bench] serving open loop: {opened['solves_per_s']:.1f} solves/s, "
           f"p99 {opened['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
     # plain FP64 path (one request at a time, two kernels per step) on a subset
+    # spread over the stream, for its throughput; its results against the FP32
+    # server at the same step count measure how far the two trajectories drift
+    # apart (most of these stop at max_steps, before equilibrium)
     idx = list(range(0, len(reqs), max(1, len(reqs) // plain_subset)))[:plain_subset]
     p64 = F.Params.from_workload(w, precision="fp64")
     times, diffs, psteps = [], [], []
@@ -156,11 +159,19 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, pl
         times.append(dt)
         psteps.append(steps)
         if i in batched:
-            # accuracy of the FP32 server against FP64 at the same step count
-            b, bsteps = batched[i]
+            b, bsteps, _ = batched[i]
             if bsteps != steps:
                 rho = serving.solve_plain(p64, reqs[i], 0.0, check_every, bsteps)[0]
             diffs.append(float(np.max(np.abs(b.reshape(rho.shape) - rho)) / np.max(np.abs(rho))))
+    # accuracy at equilibrium: requests the FP32 server converged, solved to
+    # convergence by the plain FP64 path too, final states compared
+    conv_ids = [i for i in sorted(batched) if batched[i][2] == F.FL_OK][:accuracy_subset]
+    eq_diffs = []
+    for i in conv_ids:
+        rho, steps, res, conv, dt = serving.solve_plain(p64, reqs[i], tol, check_every, max_steps)
+        if conv:
+            b = batched[i][0]
+            eq_diffs.append(float(np.max(np.abs(b.reshape(rho.shape) - rho)) / np.max(np.abs(rho))))
     plain_rate = len(idx) / sum(times)
     strip = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items() if k != "records"}
     return {
@@ -173,7 +184,10 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, pl
                        "p99_service_s": round(float(np.percentile(times, 99)), 4),
                        "mean_steps": float(np.mean(psteps))},
         "speedup_vs_plain_fp64": round(opened["solves_per_s"] / plain_rate, 2),
-        "max_rel_diff_fp32_batched_vs_fp64_plain": max(diffs) if diffs else None,
+        "equilibrium_accuracy": {"requests": len(eq_diffs),
+                                 "max_rel_diff_fp32_batched_vs_fp64_plain": max(eq_diffs) if eq_diffs else None},
+        "equal_step_drift": {"requests": len(diffs),
+                             "max_rel_diff_fp32_batched_vs_fp64_plain": max(diffs) if diffs else None},
     }
 
 

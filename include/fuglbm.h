@@ -52,6 +52,7 @@ enum { FL_EOS_PR = 0, FL_EOS_SRK = 1, FL_EOS_VDW = 2 };
 enum { FL_D2Q9 = 0, FL_D3Q19 = 1 };
 enum { FL_BGK = 0, FL_MRT = 1 };
 enum { FL_FP64 = 0, FL_FP32POP_FP64EOS = 1 };
+enum { FL_FORCE_WB = 0, FL_FORCE_STANDARD = 1 };
 
 /* One component (Sec. IV, Table tabCompProp; App. C): critical temperature and
  * pressure, acentric factor, molar mass M (step 2) and interface strength kappa
@@ -81,7 +82,13 @@ typedef struct fl_component {
  *               rest population as its offset from the initial density), EOS,
  *               logarithms, stencils and reductions in FP64
  *   force_time_level  0: the velocity of step 1 uses the previous step's force
- *               (as written in Sec. III.B, step 1); 1: this step's force */
+ *               (as written in Sec. III.B, step 1); 1: this step's force
+ *   force_model FL_FORCE_WB: well-balanced scheme (equilibrium eq. eqLBEMCb with
+ *               rho_0 = 0, forcing eq. eqLBEMCfinal3, force eq. eqforceFugLBM);
+ *               FL_FORCE_STANDARD: the standard-LBM form of Sec. V (force
+ *               eq. eqForceGen = the fugacity force + c_s^2 grad rho_i, the
+ *               standard equilibrium w_a rho_i (1 + e.u/c_s^2 + ...), Guo forcing
+ *               without the grad rho_i terms); FP64 populations only */
 typedef struct fl_params {
     int ncomp;
     const fl_component* comp;
@@ -96,6 +103,7 @@ typedef struct fl_params {
     const double* mrt_rates;
     int precision;
     int force_time_level;
+    int force_model;
 } fl_params;
 
 typedef struct fl_solver fl_solver;
@@ -103,7 +111,8 @@ typedef struct fl_solver fl_solver;
 /* Validate params; FL_EINVAL when ncomp is out of range, tau <= 0.5, a Tc, Pc or
  * M <= 0, a kappa < 0, kij not symmetric or with a non-zero diagonal, a
  * lattice dimension < 1 (or nz != 1 for D2Q9), nx*ny*nz >= 2^29 (every
- * per-array byte offset stays below 2^32), an unknown enum. */
+ * per-array byte offset stays below 2^32), an unknown enum, FL_FORCE_STANDARD
+ * with FP32 populations. */
 int fl_validate(const fl_params* p);
 
 /* Device bytes a solver needs for params (both population buffers, auxiliary

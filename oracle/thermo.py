@@ -556,3 +556,27 @@ def lattice_mixture(a, b, omega, T_over_Tc_of, T_factor, kij=None, M=None, kappa
     Tc, Pc = critical_from_ab(a, b, eos)
     T = T_factor * Tc[T_over_Tc_of]
     return Mixture(Tc, Pc, omega, T, kij=kij, eos=eos, R=1.0, M=M, kappa=kappa)
+
+
+def physical_to_lattice(names, eos="PR", a_ref=2.0 / 49.0, b_ref=2.0 / 21.0, R=1.0):
+    """Lattice-unit constants of physical components (Sec. IV, conversion rule).
+
+    The paper fixes R = 1 and, for the most volatile component (names[0]),
+    a = a_ref, b = b_ref and M = 1.  With a = Oa R^2 Tc^2 / Pc and
+    b = Ob R Tc / Pc (App. C) that fixes the lattice Tc and Pc of names[0]; the
+    temperature and pressure scales follow, and every other component keeps its
+    reduced properties (T/Tc, p/Pc) and its molar-mass ratio.  Component data
+    from Table tabCompProp.
+
+    Returns (Tc, Pc, omega, M, T_scale, p_scale): lattice value = physical value
+    times the scale (temperatures in K, pressures in bar).
+    """
+    Tc_ref, Pc_ref = critical_from_ab([a_ref], [b_ref], eos, R)
+    Pc_phys = np.array([PAPER_COMPONENTS[n][0] for n in names], dtype=np.float64)
+    Tc_phys = np.array([PAPER_COMPONENTS[n][1] for n in names], dtype=np.float64)
+    omega = np.array([PAPER_COMPONENTS[n][2] for n in names], dtype=np.float64)
+    M_phys = np.array([PAPER_COMPONENTS[n][3] for n in names], dtype=np.float64)
+    T_scale = float(Tc_ref[0]) / Tc_phys[0]
+    p_scale = float(Pc_ref[0]) / Pc_phys[0]
+    return Tc_phys * T_scale, Pc_phys * p_scale, omega, M_phys / M_phys[0], T_scale, p_scale
+

@@ -78,6 +78,18 @@ def binary_isotherm_table(mix, npts=240):
     return rows
 
 
+def e1_state(eos):
+    Tc, Pc, om, M, sT, sP = th.physical_to_lattice(["C3", "nC5"], eos)
+    kappa = [0.10, 0.15]
+    mix = th.Mixture(Tc, Pc, om, 370.03 * sT, eos=eos, R=1.0, M=M, kappa=np.array(kappa))
+    z = [0.4, 0.6]
+    fr = th.flash(mix, z, 16.547 * sP)
+    comps = [{"Tc": float(Tc[i]), "Pc": float(Pc[i]), "omega": float(om[i]), "M": float(M[i]),
+              "kappa": kappa[i]} for i in range(2)]
+    return {"components": comps, "kij": np.zeros((2, 2)).tolist(), "T": float(mix.T), "z": z,
+            "eos": eos, "T_scale_per_K": sT, "p_scale_per_bar": sP, "state": _state(fr)}
+
+
 def main():
     out = {"_note": "written by oracle/write_states.py; lattice units, R = 1"}
     # binary, T = 0.8 Tc2; z1 = 0.3 at S_V = 0.5 (the literal z1 = 0.5 has no
@@ -102,6 +114,11 @@ def main():
                                  "T": float(tmix.T), "z": z, "S_L": SL4, "state": _state(fr4)}
     out["binary_isotherm"] = {"components": _components(mix, kap_bin), "kij": np.zeros((2, 2)).tolist(),
                               "T": float(mix.T), "table": binary_isotherm_table(mix)}
+    # the paper's case of Sec. IV.A: C3/nC5, z = (0.4, 0.6), T = 370.03 K,
+    # p = 16.547 bar, PR and SRK, kappa = (0.10, 0.15), in lattice units by the
+    # conversion rule of Sec. IV
+    for eos in ("PR", "SRK"):
+        out["e1_c3c5_" + eos] = e1_state(eos)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)

@@ -187,6 +187,7 @@ int setup(fl_solver* s, const fl_params* p) {
     kp.N = (int)s->N;
     kp.eos = p->eos;
     kp.force_level = p->force_time_level;
+    kp.standard = p->force_model == FL_FORCE_STANDARD ? 1 : 0;
     kp.RT = p->R * p->T;
     kp.lnRT = std::log(kp.RT);
     kp.omega = 1.0 / p->tau;
@@ -372,6 +373,8 @@ int fl_validate(const fl_params* p) {
     if (p->collision != FL_BGK && p->collision != FL_MRT) return FL_EINVAL;
     if (p->precision != FL_FP64 && p->precision != FL_FP32POP_FP64EOS) return FL_EINVAL;
     if (p->force_time_level != 0 && p->force_time_level != 1) return FL_EINVAL;
+    if (p->force_model != FL_FORCE_WB && p->force_model != FL_FORCE_STANDARD) return FL_EINVAL;
+    if (p->force_model == FL_FORCE_STANDARD && p->precision != FL_FP64) return FL_EINVAL;
     if (!(p->tau > 0.5) || !(p->T > 0.0) || !(p->R > 0.0)) return FL_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return FL_EINVAL;
     if (D == 2 && p->nz != 1) return FL_EINVAL;

@@ -19,6 +19,7 @@ struct KParams {
     int N;                      // nx*ny*nz
     int eos;
     int force_level;            // 0: previous step's force in u; 1: this step's
+    int standard;               // 1: standard-LBM form (eqForceGen), FP64 populations only
     double RT, lnRT;
     double omega;               // 1/tau
     double cF;                  // 1 - 1/(2 tau)
@@ -189,7 +190,10 @@ struct Unroll<N, N> {
 //   momentum, traceless-stress and energy groups (P_k the orthogonal projector
 //   of group k); the conserved density row contributes nothing because
 //   sum_a v_a = 0.
-template <typename L, typename T, bool MRT, bool REST_OFFSET>
+//   STD: the standard equilibrium w_a rho (1 + B_a) (every direction carries
+//   w_a rho instead of the rest one carrying rho); the caller passes G = 0 so
+//   the forcing is Guo's term without the grad rho part.
+template <typename L, typename T, bool MRT, bool REST_OFFSET, bool STD = false>
 __device__ __forceinline__ void collide(const KParams& kp, const CompState<T>& c, const T (&gv)[L::Q],
                                         T moving_sum, T (&out)[L::Q]) {
     constexpr int Q = L::Q;
@@ -201,7 +205,10 @@ __device__ __forceinline__ void collide(const KParams& kp, const CompState<T>& c
     Unroll<0, Q>::run([&](auto ai) {
         constexpr int a = decltype(ai)::value;
         const T sh = geq_shape<L, T, a>(c, uu);
-        if constexpr (a == 0) {
+        if constexpr (STD) {
+            static_assert(!REST_OFFSET, "standard form: FP64 populations only");
+            neq[a] = gv[a] - (T(L::w[a]) * c.rho + sh);
+        } else if constexpr (a == 0) {
             if constexpr (REST_OFFSET)
                 neq[0] = -moving_sum - sh;      // g_0 - rho - w_0 rho B_0
             else

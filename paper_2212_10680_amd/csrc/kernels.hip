@@ -182,10 +182,13 @@ __device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at,
             unit_offset(k, 1, px, py, pz);
             const double dl = (lnf_at(i, px, py, pz) - lnf_at(i, -px, -py, -pz)) / 2.0;
             const double dm = kp.sk[i] * (mh[2 * k] - mh[2 * k + 1]) / 2.0;
-            const double f = -rc * (kp.RT * dl + dm);
+            double f = -rc * (kp.RT * dl + dm);
+            const double gr = kp.M[i] * (rt_at(i, px, py, pz) - rt_at(i, -px, -py, -pz)) / 2.0;
+            if constexpr (sizeof(T) == 8)
+                if (kp.standard) f += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
             Fs[k] += f;
             F[i][k] = T(f);
-            G[i][k] = T(kp.M[i] * (rt_at(i, px, py, pz) - rt_at(i, -px, -py, -pz)) / 2.0);
+            G[i][k] = T(gr);
         }
     }
 }
@@ -258,7 +261,15 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         cs.Fx = F[c][0]; cs.Fy = F[c][1]; cs.Fz = F[c][2];
         cs.Gx = G[c][0]; cs.Gy = G[c][1]; cs.Gz = G[c][2];
         T out[Q];
-        collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
+        bool std_form = false;
+        if constexpr (sizeof(P) == 8) std_form = kp.standard != 0;
+        if constexpr (sizeof(P) == 8) {
+            if (std_form) {
+                cs.Gx = cs.Gy = cs.Gz = T(0);  // Guo forcing without the grad rho part
+                collide<L, T, MRT, false, true>(kp, cs, gv[c], T(mov[c]), out);
+            }
+        }
+        if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
         {
@@ -499,7 +510,10 @@ __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restri
         for (int a = 0; a < Q; ++a) {
             const double eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
             double ge = L::w[a] * rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-            if (a == 0) ge += rho - ref;
+            if (kp.standard)
+                ge += L::w[a] * rho;  // standard equilibrium w_a rho (1 + ...)
+            else if (a == 0)
+                ge += rho - ref;
             g[(size_t)(c * Q + a) * N + n] = (P)ge;
         }
     }

@@ -49,12 +49,13 @@ class Workload:
     ncomp: int
     kappa_scale: float = 0.5
     W: float = 4.0
-    SV: float = 0.5
+    SV: float | None = 0.5       # None: the flash state's vapor saturation
     radius: float = 0.0
     separation: float = 0.0
     u0: float = 0.0
     noise: float = 0.0
     seed: int = 0
+    eos: str = "PR"
     extra: dict = field(default_factory=dict)
 
     @property
@@ -72,6 +73,10 @@ class Workload:
         for c in comps:
             c["kappa"] *= self.kappa_scale
         return comps, np.array(st["kij"], dtype=np.float64), float(st["T"])
+
+    @property
+    def vapor_saturation(self):
+        return self.SV if self.SV is not None else float(states()[self.state_key]["state"]["S_V"])
 
     def phase_densities(self):
         st = states()[self.state_key]["state"]
@@ -104,6 +109,13 @@ WORKLOADS = {
     "ternary_droplets_3d": Workload("ternary_droplets_3d", "D3Q19", (256, 256, 256), "MRT", 0.8,
                                     "fp32", 20000, "ternary_droplets3d", "two_droplets", 3,
                                     radius=30.0, separation=70.0, u0=0.02),
+    # the paper's flat-interface case of Sec. IV.A: C3/nC5 (z = 0.4/0.6) at
+    # 370.03 K and 16.547 bar, D2Q9 400 x 2, tau = 0.8, kappa = (0.10, 0.15)
+    # as given, W = 8, S_V from the flash, 1e6 steps; PR and SRK
+    "e1_c3c5_pr": Workload("e1_c3c5_pr", "D2Q9", (400, 2), "BGK", 0.8, "fp64", 1000000,
+                           "e1_c3c5_PR", "slab", 2, kappa_scale=1.0, W=8.0, SV=None, eos="PR"),
+    "e1_c3c5_srk": Workload("e1_c3c5_srk", "D2Q9", (400, 2), "BGK", 0.8, "fp64", 1000000,
+                            "e1_c3c5_SRK", "slab", 2, kappa_scale=1.0, W=8.0, SV=None, eos="SRK"),
 }
 
 
@@ -136,7 +148,7 @@ def initial_field(w: Workload, seed=None, rho_LV=None):
     nc = len(rho_L)
     u = None
     if w.geometry == "slab":
-        rho = np.stack([slab_profile(x, nx, rho_L[i], rho_V[i], w.SV, w.W) for i in range(nc)])
+        rho = np.stack([slab_profile(x, nx, rho_L[i], rho_V[i], w.vapor_saturation, w.W) for i in range(nc)])
     elif w.geometry == "droplet":
         xc, yc, zc = nx / 2.0, ny / 2.0, nz / 2.0
         r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2 + ((z - zc) ** 2 if nz > 1 else 0.0))

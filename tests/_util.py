@@ -7,16 +7,17 @@ from oracle import thermo as th
 from paper_2212_10680_amd import workloads as wl
 
 
-def mixture_of(w, eos="PR"):
+def mixture_of(w, eos=None):
+    eos = eos or w.eos
     comps, kij, T = w.thermo()
     return th.Mixture([c["Tc"] for c in comps], [c["Pc"] for c in comps],
                       [c["omega"] for c in comps], T, kij=kij, M=[c["M"] for c in comps],
                       kappa=[c["kappa"] for c in comps], eos=eos)
 
 
-def oracle_for(w, eos="PR", force_level=0, mrt_S=None):
+def oracle_for(w, eos=None, force_level=0, mrt_S=None, standard_force=False):
     return lbm.OracleLBM(mixture_of(w, eos), w.lattice, w.shape, tau=w.tau, collision=w.collision,
-                         force_level=force_level, mrt_S=mrt_S)
+                         force_level=force_level, mrt_S=mrt_S, standard_force=standard_force)
 
 
 def direction_map(lattice, gpu_e):
@@ -44,3 +45,44 @@ def smooth_3d_field(w, amp=0.01):
 
 def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def bulk_values(rho):
+    """Bulk molar densities of a flat-interface profile (R-17): the mean over
+    the central quarter of the liquid and of the vapor region (an even number of
+    consecutive nodes), the regions split at rho~ = (max + min) / 2 along the
+    periodic axis.  rho: [nc, n] (one row of the lattice).  Returns
+    (rho_liquid [nc], rho_vapor [nc])."""
+    rho = np.asarray(rho, dtype=np.float64)
+    tot = rho.sum(axis=0)
+    n = tot.size
+    liquid = tot > 0.5 * (tot.max() + tot.min())
+    idx = np.arange(n)
+
+    def central(ix):
+        # circular mean locates the centre of a region that may wrap around
+        c = (np.angle(np.exp(2j * np.pi * ix / n).mean()) * n / (2 * np.pi)) % n
+        d = (ix - c + n / 2) % n - n / 2
+        sel = ix[np.abs(d) <= 0.125 * ix.size]
+        # an even number of consecutive nodes: the even/odd alternation that
+        # central differences leave in mu (R-18) cancels in the mean
+        if sel.size % 2:
+            sel = ix[(np.abs(d) <= 0.125 * ix.size) & (d != d[np.abs(d) <= 0.125 * ix.size].max())]
+        return sel
+
+    return rho[:, central(idx[liquid])].mean(axis=1), rho[:, central(idx[~liquid])].mean(axis=1)
+
+
+def flash_errors_percent(mix, z, rho_L, rho_V):
+    """Relative errors (eq. eqerror, in %) of bulk density and mole fractions
+    against a PT flash of the feed z at the liquid bulk's EOS pressure."""
+    fr = th.flash(mix, z, mix.pressure(rho_L))
+    assert fr.two_phase
+    err = lambda a, b: 100.0 * abs(a - b) / b
+    return {
+        "liquid": {"density": err(rho_L.sum(), 1.0 / fr.vL), "x_C3": err(rho_L[0] / rho_L.sum(), fr.x[0]),
+                   "x_C5": err(rho_L[1] / rho_L.sum(), fr.x[1])},
+        "vapor": {"density": err(rho_V.sum(), 1.0 / fr.vV), "x_C3": err(rho_V[0] / rho_V.sum(), fr.y[0]),
+                  "x_C5": err(rho_V[1] / rho_V.sum(), fr.y[1])},
+    }
+

@@ -47,6 +47,7 @@ def test_validate_accepts_workloads(lib):
         for prec in ("fp64", "fp32"):
             p = F.Params.from_workload(w, precision=prec)
             assert p.validate() == F.FL_OK, name
+        assert F.Params.from_workload(w, precision="fp64", force_model="standard").validate() == F.FL_OK
 
 
 @pytest.mark.parametrize("mut", [
@@ -59,6 +60,10 @@ def test_validate_accepts_workloads(lib):
     lambda p: setattr(p.c, "lattice", 2),
     lambda p: setattr(p.c, "precision", 3),
     lambda p: setattr(p.c, "force_time_level", 2),
+    lambda p: setattr(p.c, "force_model", 2),
+    lambda p: (setattr(p.c, "force_model", 1), setattr(p.c, "precision", 1)),  # standard form: FP64 only
+    lambda p: (setattr(p.c, "lattice", 1), setattr(p.c, "nx", 1024), setattr(p.c, "ny", 1024),
+               setattr(p.c, "nz", 512)),                                     # 2^29 nodes
     lambda p: setattr(p._comp[0], "Tc", -1.0),
     lambda p: setattr(p._comp[1], "M", 0.0),
     lambda p: setattr(p._comp[0], "kappa", -0.1),

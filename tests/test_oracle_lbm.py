@@ -95,6 +95,53 @@ def test_forcing_moments(name):
 
 
 @pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_standard_variant_moments(name):
+    """Standard-LBM form (Sec. V, eqForceGen): the equilibrium carries the
+    lattice pressure, moments rho, rho u, rho u u + c_s^2 rho I, and the
+    forcing term is Guo's, moments 0, F, u F + F u (no grad rho part)."""
+    o = lbm.OracleLBM(binary_mix(), name, (4, 4) if name == "D2Q9" else (4, 4, 4), standard_force=True)
+    e = lat.lattice(name)[0].astype(float)
+    D = o.D
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho = rng.uniform(0.5, 5)
+        u = rng.uniform(-0.1, 0.1, D)
+        geq = o.equilibrium(rho, u)
+        assert abs(geq.sum() - rho) < 1e-14 * rho
+        assert np.allclose(geq @ e, rho * u, atol=1e-14)
+        assert np.allclose(np.einsum("a,ai,aj->ij", geq, e, e),
+                           rho * np.outer(u, u) + CS2 * rho * np.eye(D), atol=1e-14)
+        F, g = rng.normal(size=D), rng.normal(size=D)
+        Fa = o.forcing(F, g, u)
+        assert abs(Fa.sum()) < 1e-14
+        assert np.allclose(Fa @ e, F, atol=1e-14)
+        assert np.allclose(np.einsum("a,ai,aj->ij", Fa, e, e), np.outer(u, F) + np.outer(F, u), atol=1e-13)
+
+
+def test_standard_variant_uniform_fixed_point_and_mass():
+    """A uniform state is a fixed point of the standard form (every gradient
+    vanishes); a non-uniform one conserves each component's mass."""
+    mix = binary_mix()
+    nx = 32
+    o = lbm.OracleLBM(mix, "D2Q9", (nx, 4), tau=1.0, standard_force=True)
+    r0 = np.stack([np.full(nx * 4, 2.0), np.full(nx * 4, 3.0)])
+    o.init(r0)
+    g0 = o.g.copy()
+    o.run(50)
+    assert np.max(np.abs(o.g - g0)) < 1e-14
+    o2 = lbm.OracleLBM(mix, "D2Q9", (nx, 4), tau=1.0, standard_force=True)
+    o2.init(np.ascontiguousarray(np.tile(slab(nx), (1, 4))))
+    m0 = o2.mass()
+    o2.run(200)
+    assert np.allclose(o2.mass(), m0, rtol=1e-13)
+    # the standard form differs from the well-balanced one away from uniform states
+    o3 = lbm.OracleLBM(mix, "D2Q9", (nx, 4), tau=1.0)
+    o3.init(np.ascontiguousarray(np.tile(slab(nx), (1, 4))))
+    o3.run(200)
+    assert np.max(np.abs(o3.fields()["rho_molar"] - o2.fields()["rho_molar"])) > 1e-6
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
 def test_mrt_basis_orthogonal(name):
     M, groups = lat.mrt_basis(name)
     G = M @ M.T
