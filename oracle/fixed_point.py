@@ -84,3 +84,22 @@ def solve(mix: Mixture, rho0, kappa, eta=None, totals=None, tol=1e-14, maxit=60)
         rho = rho + step[:nc * n].reshape(nc, n)
         lam = lam + step[nc * n:]
     return rho, lam, res_norm
+
+
+def interfacial_tension(mix: Mixture, rho, kappa, n_interfaces=2):
+    """eq. eqMCsigma on a discrete flat-interface profile rho [nc, n] (periodic
+    along the row): the integral of sum_ij kappa_ij (d rho~_i/dx)(d rho~_j/dx)
+    with central differences (eq1stder) summed over the row, divided by the
+    number of interfaces the row holds (a periodic slab has two)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    kappa = np.asarray(kappa, dtype=np.float64)
+    kij = np.sqrt(np.outer(kappa, kappa))
+    d = 0.5 * (np.roll(rho, -1, axis=1) - np.roll(rho, 1, axis=1))
+    return float(np.einsum("ij,ix,jx->", kij, d, d)) / n_interfaces
+
+
+def lamb_period(sigma, rho_liquid_mass, R_e, n=2):
+    """eq. eqPeriod: period of the n-th shape mode of a 2-D droplet,
+    T = 2 pi [n (n^2 - 1) sigma / (rho_L R_e^3)]^(-1/2)."""
+    return 2.0 * np.pi / np.sqrt(n * (n * n - 1) * sigma / (rho_liquid_mass * R_e ** 3))
+

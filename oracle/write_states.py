@@ -90,6 +90,50 @@ def e1_state(eos):
             "eos": eos, "T_scale_per_K": sT, "p_scale_per_bar": sP, "state": _state(fr)}
 
 
+def e5_state():
+    """Sec. IV.C: C1/C2/C3, z = (0.4, 0.3, 0.3), PR, 216.483 K, 20.684 bar."""
+    Tc, Pc, om, M, sT, sP = th.physical_to_lattice(["C1", "C2", "C3"], "PR")
+    kappa = [0.05, 0.10, 0.15]
+    mix = th.Mixture(Tc, Pc, om, 216.483 * sT, eos="PR", R=1.0, M=M, kappa=np.array(kappa))
+    z = [0.4, 0.3, 0.3]
+    fr = th.flash(mix, z, 20.684 * sP)
+    comps = [{"Tc": float(Tc[i]), "Pc": float(Pc[i]), "omega": float(om[i]), "M": float(M[i]),
+              "kappa": kappa[i]} for i in range(3)]
+    return {"components": comps, "kij": np.zeros((3, 3)).tolist(), "T": float(mix.T), "z": z,
+            "eos": "PR", "T_scale_per_K": sT, "p_scale_per_bar": sP, "state": _state(fr)}
+
+
+def e6_state():
+    """Sec. IV.D: C2/nC5 at 387.70 K, uniform x = (0.62, 0.38) at the molar
+    density whose EOS pressure is 50 bar (the one real root)."""
+    Tc, Pc, om, M, sT, sP = th.physical_to_lattice(["C2", "nC5"], "PR")
+    kappa = [0.10, 0.15]
+    mix = th.Mixture(Tc, Pc, om, 387.70 * sT, eos="PR", R=1.0, M=M, kappa=np.array(kappa))
+    x = np.array([0.62, 0.38])
+    roots = mix.volume_roots(50.0 * sP, x)
+    assert len(roots) == 1
+    rho = x / roots[0]
+    comps = [{"Tc": float(Tc[i]), "Pc": float(Pc[i]), "omega": float(om[i]), "M": float(M[i]),
+              "kappa": kappa[i]} for i in range(2)]
+    return {"components": comps, "kij": np.zeros((2, 2)).tolist(), "T": float(mix.T), "z": x.tolist(),
+            "eos": "PR", "T_scale_per_K": sT, "p_scale_per_bar": sP,
+            "state": {"p": float(mix.pressure(rho)), "rho_uniform": rho.tolist()}}
+
+
+def e7_state():
+    """Sec. IV.E: C3/nC5 flash with PR at 340 K and 5 bar (density ratio
+    50.97); the phase compositions do not depend on the feed inside the
+    two-phase region, so the feed is z = (0.5, 0.5)."""
+    Tc, Pc, om, M, sT, sP = th.physical_to_lattice(["C3", "nC5"], "PR")
+    kappa = [0.05, 0.10]
+    mix = th.Mixture(Tc, Pc, om, 340.0 * sT, eos="PR", R=1.0, M=M, kappa=np.array(kappa))
+    fr = th.flash(mix, [0.5, 0.5], 5.0 * sP)
+    comps = [{"Tc": float(Tc[i]), "Pc": float(Pc[i]), "omega": float(om[i]), "M": float(M[i]),
+              "kappa": kappa[i]} for i in range(2)]
+    return {"components": comps, "kij": np.zeros((2, 2)).tolist(), "T": float(mix.T), "z": [0.5, 0.5],
+            "eos": "PR", "T_scale_per_K": sT, "p_scale_per_bar": sP, "state": _state(fr)}
+
+
 def main():
     out = {"_note": "written by oracle/write_states.py; lattice units, R = 1"}
     # binary, T = 0.8 Tc2; z1 = 0.3 at S_V = 0.5 (the literal z1 = 0.5 has no
@@ -119,6 +163,9 @@ def main():
     # conversion rule of Sec. IV
     for eos in ("PR", "SRK"):
         out["e1_c3c5_" + eos] = e1_state(eos)
+    out["e5_c1c2c3"] = e5_state()
+    out["e6_c2c5_spinodal"] = e6_state()
+    out["e7_c3c5_droplet"] = e7_state()
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)

@@ -6,9 +6,9 @@ This module holds no step of the lattice update and no thermodynamics: it only
   phase densities) from ``workload_states.json``, which the oracle's state
   writer produced, and
 * builds initial molar-density fields with the paper's geometry recipes: the
-  tanh slab of eq. ``eqInit`` (Sec. IV.A) and the tanh droplet of
+  tanh slab of eq. ``eqInit`` (Sec. IV.A), the tanh droplet of
   eq. ``eqInit2D`` (Sec. IV.E, h = 1 for a circle, extended to a sphere in 3-D),
-  plus seeded multiplicative noise (numpy PCG64).
+  a uniform state (Sec. IV.D), plus seeded multiplicative noise (numpy PCG64).
 
 Both the GPU path and the oracle are fed from here, so they see identical bits.
 """
@@ -51,6 +51,7 @@ class Workload:
     W: float = 4.0
     SV: float | None = 0.5       # None: the flash state's vapor saturation
     radius: float = 0.0
+    h: float = 1.0               # y semi-axis / x semi-axis of a droplet (eqInit2D)
     separation: float = 0.0
     u0: float = 0.0
     noise: float = 0.0
@@ -116,6 +117,20 @@ WORKLOADS = {
                            "e1_c3c5_PR", "slab", 2, kappa_scale=1.0, W=8.0, SV=None, eos="PR"),
     "e1_c3c5_srk": Workload("e1_c3c5_srk", "D2Q9", (400, 2), "BGK", 0.8, "fp64", 1000000,
                             "e1_c3c5_SRK", "slab", 2, kappa_scale=1.0, W=8.0, SV=None, eos="SRK"),
+    # Sec. IV.C: C1/C2/C3 (z = 0.4/0.3/0.3) at 216.483 K and 20.684 bar, D2Q9
+    # 200 x 2, tau = 1, kappa = (0.05, 0.10, 0.15), W = 4, S_V from the flash
+    "e5_c1c2c3": Workload("e5_c1c2c3", "D2Q9", (200, 2), "BGK", 1.0, "fp64", 1000000,
+                          "e5_c1c2c3", "slab", 3, kappa_scale=1.0, W=4.0, SV=None),
+    # Sec. IV.E: elliptical C3/nC5 droplet (R0 = 30, h = 0.9, W = 4) in PR at
+    # 340 K and 5 bar (density ratio 50.97), D2Q9 200 x 200, tau = 0.85,
+    # kappa = (0.05, 0.10), 4000 steps
+    "e7_droplet": Workload("e7_droplet", "D2Q9", (200, 200), "BGK", 0.85, "fp64", 4000,
+                           "e7_c3c5_droplet", "droplet", 2, kappa_scale=1.0, radius=30.0, h=0.9),
+    # Sec. IV.D: C2/nC5 spinodal decomposition from a uniform x = (0.62, 0.38)
+    # at 50 bar and 387.70 K, D2Q9 200 x 200, tau = 1.15, kappa = (0.10, 0.15);
+    # +-1 % seeded fluctuation of the total density (amplitude not given)
+    "e6_spinodal": Workload("e6_spinodal", "D2Q9", (200, 200), "BGK", 1.15, "fp64", 500000,
+                            "e6_c2c5_spinodal", "uniform", 2, kappa_scale=1.0, noise=0.01),
 }
 
 
@@ -141,8 +156,15 @@ def droplet_indicator(r, R0, W):
 
 def initial_field(w: Workload, seed=None, rho_LV=None):
     """Molar densities [nc, nz, ny, nx] and velocity [D, nz, ny, nx] (or None)."""
-    rho_L, rho_V, _ = w.phase_densities() if rho_LV is None else (*rho_LV, None)
     x, y, z = _grid(w.shape)
+    if w.geometry == "uniform":
+        # a uniform state with a seeded multiplicative fluctuation of the total
+        # density (the composition stays uniform)
+        r0 = np.array(states()[w.state_key]["state"]["rho_uniform"])
+        rng = np.random.Generator(np.random.PCG64(w.seed if seed is None else seed))
+        fluct = 1.0 + w.noise * rng.uniform(-1.0, 1.0, x.shape)
+        return np.ascontiguousarray(np.stack([r0[i] * fluct for i in range(len(r0))])), None
+    rho_L, rho_V, _ = w.phase_densities() if rho_LV is None else (*rho_LV, None)
     nx, ny = w.shape[0], w.shape[1]
     nz = w.shape[2] if len(w.shape) == 3 else 1
     nc = len(rho_L)
@@ -151,7 +173,7 @@ def initial_field(w: Workload, seed=None, rho_LV=None):
         rho = np.stack([slab_profile(x, nx, rho_L[i], rho_V[i], w.vapor_saturation, w.W) for i in range(nc)])
     elif w.geometry == "droplet":
         xc, yc, zc = nx / 2.0, ny / 2.0, nz / 2.0
-        r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2 + ((z - zc) ** 2 if nz > 1 else 0.0))
+        r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2 / w.h ** 2 + ((z - zc) ** 2 if nz > 1 else 0.0))
         phi = droplet_indicator(r, w.radius, w.W)
         rho = np.stack([rho_V[i] + (rho_L[i] - rho_V[i]) * phi for i in range(nc)])
     elif w.geometry == "two_droplets":

@@ -73,16 +73,44 @@ def bulk_values(rho):
     return rho[:, central(idx[liquid])].mean(axis=1), rho[:, central(idx[~liquid])].mean(axis=1)
 
 
-def flash_errors_percent(mix, z, rho_L, rho_V):
+def flash_errors_percent(mix, z, rho_L, rho_V, names=("C3", "C5")):
     """Relative errors (eq. eqerror, in %) of bulk density and mole fractions
-    against a PT flash of the feed z at the liquid bulk's EOS pressure."""
+    against a PT flash of the feed z at the liquid bulk's EOS pressure.
+    Keys: "density" and "x_<name>" per component."""
     fr = th.flash(mix, z, mix.pressure(rho_L))
     assert fr.two_phase
     err = lambda a, b: 100.0 * abs(a - b) / b
-    return {
-        "liquid": {"density": err(rho_L.sum(), 1.0 / fr.vL), "x_C3": err(rho_L[0] / rho_L.sum(), fr.x[0]),
-                   "x_C5": err(rho_L[1] / rho_L.sum(), fr.x[1])},
-        "vapor": {"density": err(rho_V.sum(), 1.0 / fr.vV), "x_C3": err(rho_V[0] / rho_V.sum(), fr.y[0]),
-                  "x_C5": err(rho_V[1] / rho_V.sum(), fr.y[1])},
-    }
+    out = {}
+    for phase, r, v, comp in (("liquid", rho_L, fr.vL, fr.x), ("vapor", rho_V, fr.vV, fr.y)):
+        d = {"density": err(r.sum(), 1.0 / v)}
+        for i, n in enumerate(names):
+            d["x_" + n] = err(r[i] / r.sum(), comp[i])
+        out[phase] = d
+    return out
+
+
+def half_width(line, centre, level):
+    """Distance from centre to where the profile line (periodic) falls through
+    level on each side, by linear interpolation between nodes (the droplet
+    boundary of Sec. IV.E); returns the mean of the two sides."""
+    n = line.size
+    out = []
+    for step in (1, -1):
+        k = 0
+        while line[(centre + step * (k + 1)) % n] >= level:
+            k += 1
+            if k >= n // 2:
+                raise ValueError("no crossing")
+        a, b = line[(centre + step * k) % n], line[(centre + step * (k + 1)) % n]
+        out.append(k + (a - level) / (a - b))
+    return 0.5 * (out[0] + out[1])
+
+
+def damped_period(t, r, guess):
+    """Period of r(t) = c + A exp(-t/d) cos(2 pi t / T + phi) by least squares."""
+    from scipy.optimize import curve_fit
+    f = lambda t, c, A, d, T, ph: c + A * np.exp(-t / d) * np.cos(2 * np.pi * t / T + ph)
+    p0 = [float(np.mean(r)), float(r[0] - np.mean(r)), 4.0 * guess, guess, 0.0]
+    p, _ = curve_fit(f, t, r, p0=p0, maxfev=20000)
+    return abs(p[3]), p
 
