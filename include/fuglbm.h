@@ -110,9 +110,10 @@ typedef struct fl_solver fl_solver;
 
 /* Validate params; FL_EINVAL when ncomp is out of range, tau <= 0.5, a Tc, Pc or
  * M <= 0, a kappa < 0, kij not symmetric or with a non-zero diagonal, a
- * lattice dimension < 1 (or nz != 1 for D2Q9), nx*ny*nz >= 2^29 (every
- * per-array byte offset stays below 2^32), an unknown enum, FL_FORCE_STANDARD
- * with FP32 populations. */
+ * lattice dimension < 1 (or nz != 1 for D2Q9), N = nx*ny*nz >= 2^29 or
+ * N * ncomp * (8 for FP64, 4 for FP32 populations) >= 2^32 (every per-array
+ * byte offset stays below 2^32), an unknown enum, FL_FORCE_STANDARD with FP32
+ * populations. */
 int fl_validate(const fl_params* p);
 
 /* Device bytes a solver needs for params (both population buffers, auxiliary

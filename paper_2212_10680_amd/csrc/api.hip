@@ -379,7 +379,10 @@ int fl_validate(const fl_params* p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return FL_EINVAL;
     if (D == 2 && p->nz != 1) return FL_EINVAL;
     const double N = (double)p->nx * p->ny * p->nz;
-    if (N >= 536870912.0) return FL_EINVAL;  // 2^29: byte offsets within one array < 2^32
+    // byte offsets within one array stay below 2^32: the FP64 fields (8 B per
+    // node and component) and one direction's populations (N_c per node)
+    if (N >= 536870912.0) return FL_EINVAL;  // 2^29
+    if (N * p->ncomp * (p->precision == FL_FP64 ? 8.0 : 4.0) >= 4294967296.0) return FL_EINVAL;
     for (int i = 0; i < p->ncomp; ++i) {
         const fl_component& c = p->comp[i];
         if (!(c.Tc > 0) || !(c.Pc > 0) || !(c.M > 0) || !(c.kappa >= 0) || !std::isfinite(c.omega))

@@ -1,13 +1,16 @@
 // HIP kernels of the per-step update and its auxiliary passes (gfx950).
 //
 // Layout in HBM (structure of arrays, node index n = x + nx*(y + ny*z)):
-//   populations  g[c][a][n]   (P = double, or float in the FP32 form where the
-//                             rest slot a = 0 holds g_0 minus rref[c][n])
+//   populations  g[a][n][c]   direction-major, the N_c components of one
+//                             direction of one node side by side (one vector
+//                             load or store per direction and node); P = double,
+//                             or float in the FP32 form where the rest slot
+//                             a = 0 holds g_0 minus rref[n][c]
 //   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64);
 //                             plane c = N_c of lnf holds phi[n] = sum_j sqrt(kappa_j) rho~_j
-//   fsum[k][n]                sum_i F_i of the previous step (population precision;
+//   fsum[n][k]                sum_i F_i of the previous step (population precision;
 //                             read from one buffer, written to another)
-//   rref[c][n]                rest-population reference (FP32 form only)
+//   rref[n][c]                rest-population reference (FP32 form only)
 //
 // Step = k_moments_eos (steps 1-5: reads every population once, writes rt and
 // ln f) followed by k_collide_stream (steps 6-9: reads the node's populations,
@@ -29,13 +32,19 @@ __device__ __forceinline__ void st(T* base, unsigned byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Start of direction a's block of N nodes x N_c components.
+template <int NC, typename P>
+__device__ __forceinline__ const P* dir_base(const P* g, int a, size_t N) { return g + (size_t)a * N * NC; }
+template <int NC, typename P>
+__device__ __forceinline__ P* dir_base(P* g, int a, size_t N) { return g + (size_t)a * N * NC; }
+
 template <typename L, int NC, typename P>
 __device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t N, P (&gv)[NC][L::Q]) {
-    const unsigned off = (unsigned)n * (unsigned)sizeof(P);
+    const unsigned off = (unsigned)n * (unsigned)(NC * sizeof(P));
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int a = 0; a < L::Q; ++a)
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) gv[c][a] = ld(g + (size_t)(c * L::Q + a) * N, off);
+        for (int c = 0; c < NC; ++c) gv[c][a] = ld(dir_base<NC>(g, a, N), off + c * (unsigned)sizeof(P));
 }
 
 // rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
@@ -48,7 +57,7 @@ __device__ __forceinline__ void densities(const P (&gv)[NC][L::Q], const float* 
 #pragma unroll
         for (int a = 1; a < L::Q; ++a) m += (double)gv[c][a];
         double r0 = (double)gv[c][0];
-        if constexpr (sizeof(P) == 4) r0 += (double)ld(rref + (size_t)c * N, (unsigned)n * 4u);
+        if constexpr (sizeof(P) == 4) r0 += (double)ld(rref, ((unsigned)n * NC + c) * 4u);
         moving[c] = m;
         rho[c] = r0 + m;
     }
@@ -219,18 +228,18 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         if (dx) m += step[0][dx > 0];
         if (dy) m += step[1][dy > 0];
         if (D == 3 && dz) m += step[2][dz > 0];
-        return (unsigned)m * (unsigned)sizeof(P);
+        return (unsigned)m * (unsigned)(NC * sizeof(P));   // byte offset of node m's components
     };
 
     P gv[NC][Q];
     if constexpr (NTLD) {
-        const unsigned off = (unsigned)n * (unsigned)sizeof(P);
+        const unsigned off = (unsigned)n * (unsigned)(NC * sizeof(P));
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+        for (int a = 0; a < Q; ++a)
 #pragma unroll
-            for (int a = 0; a < Q; ++a)
-                gv[c][a] = __builtin_nontemporal_load(
-                    reinterpret_cast<const P*>(reinterpret_cast<const char*>(g + (size_t)(c * Q + a) * N) + off));
+            for (int c = 0; c < NC; ++c)
+                gv[c][a] = __builtin_nontemporal_load(reinterpret_cast<const P*>(
+                    reinterpret_cast<const char*>(dir_base<NC>(g, a, N)) + off + c * sizeof(P)));
     } else {
         load_pops<L, NC, P>(g, n, N, gv);
     }
@@ -250,9 +259,26 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : (double)ld(fsum_in + (size_t)k * N, (unsigned)n * (unsigned)sizeof(P));
+        const double fk = kp.force_level ? Fs[k] : (double)ld(fsum_in, ((unsigned)n * D + k) * (unsigned)sizeof(P));
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
+    // Push: direction a goes to n + e_a.  With two components both values of a
+    // direction leave as one vector store (all outputs live at once); with
+    // more, each component is stored right after its collision (register
+    // pressure), and L2 merges the interleaved partial lines.
+    constexpr bool kJoint = NC <= 2;
+    T out[kJoint ? NC : 1][Q];
+    auto push = [&](int c, const T (&o)[Q]) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            P* dst = dir_base<NC>(gn, a, N);
+            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]) + c * (unsigned)sizeof(P);
+            if (nt)
+                __builtin_nontemporal_store(o[a], (P*)((char*)dst + off));
+            else
+                st(dst, off, o[a]);
+        }
+    };
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         CompState<T> cs;
@@ -260,29 +286,35 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         cs.ux = T(u[0]); cs.uy = T(u[1]); cs.uz = T(u[2]);
         cs.Fx = F[c][0]; cs.Fy = F[c][1]; cs.Fz = F[c][2];
         cs.Gx = G[c][0]; cs.Gy = G[c][1]; cs.Gz = G[c][2];
-        T out[Q];
+        T (&oc)[Q] = out[kJoint ? c : 0];
         bool std_form = false;
         if constexpr (sizeof(P) == 8) std_form = kp.standard != 0;
         if constexpr (sizeof(P) == 8) {
             if (std_form) {
                 cs.Gx = cs.Gy = cs.Gz = T(0);  // Guo forcing without the grad rho part
-                collide<L, T, MRT, false, true>(kp, cs, gv[c], T(mov[c]), out);
+                collide<L, T, MRT, false, true>(kp, cs, gv[c], T(mov[c]), oc);
             }
         }
-        if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), out);
+        if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), oc);
+        if constexpr (!kJoint) push(c, oc);
+    }
+    if constexpr (kJoint) {
+        using V = P __attribute__((ext_vector_type(NC)));
 #pragma unroll
-        for (int a = 0; a < Q; ++a)
-        {
-            P* dst = gn + (size_t)(c * Q + a) * N;
-            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]);
+        for (int a = 0; a < Q; ++a) {
+            V v;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = out[c][a];
+            V* dst = reinterpret_cast<V*>(reinterpret_cast<char*>(dir_base<NC>(gn, a, N)) +
+                                          nbr_off(L::ex[a], L::ey[a], L::ez[a]));
             if (nt)
-                __builtin_nontemporal_store(out[a], (P*)((char*)dst + off));
+                __builtin_nontemporal_store(v, dst);
             else
-                st(dst, off, out[a]);
+                *dst = v;
         }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) st(fsum_out + (size_t)k * N, (unsigned)n * (unsigned)sizeof(P), (P)Fs[k]);
+    for (int k = 0; k < D; ++k) st(fsum_out, ((unsigned)n * D + k) * (unsigned)sizeof(P), (P)Fs[k]);
 }
 
 // Steps 6-9 at node n reading the FP64 fields straight from global memory.
@@ -503,7 +535,7 @@ __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restri
         double ref = 0.0;
         if constexpr (sizeof(P) == 4) {
             const float rf = (float)rho;
-            rref[(size_t)c * N + n] = rf;
+            rref[(size_t)n * NC + c] = rf;
             ref = (double)rf;
         }
 #pragma unroll
@@ -514,11 +546,11 @@ __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restri
                 ge += L::w[a] * rho;  // standard equilibrium w_a rho (1 + ...)
             else if (a == 0)
                 ge += rho - ref;
-            g[(size_t)(c * Q + a) * N + n] = (P)ge;
+            g[((size_t)a * N + n) * NC + c] = (P)ge;
         }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) fsum[(size_t)k * N + n] = (P)0;
+    for (int k = 0; k < D; ++k) fsum[(size_t)n * D + k] = (P)0;
 }
 
 // ------------------------------------------------------------ output fields
@@ -551,7 +583,7 @@ __global__ __launch_bounds__(256) void k_fields(KParams kp, const P* __restrict_
         }
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) uout[(size_t)k * N + n] = (j[k] + 0.5 * (double)fsum[(size_t)k * N + n]) / rtot;
+    for (int k = 0; k < D; ++k) uout[(size_t)k * N + n] = (j[k] + 0.5 * (double)fsum[(size_t)n * D + k]) / rtot;
     double p;
     eos_lnf<NC>(kp, r, lf, &p);
     pout[n] = p;
@@ -571,9 +603,9 @@ __global__ __launch_bounds__(256) void k_export_pops(KParams kp, const P* __rest
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) {
-            double v = (double)g[(size_t)(c * L::Q + a) * N + n];
+            double v = (double)g[((size_t)a * N + n) * NC + c];
             if constexpr (sizeof(P) == 4)
-                if (a == 0) v += (double)rref[(size_t)c * N + n];
+                if (a == 0) v += (double)rref[(size_t)n * NC + c];
             out[(size_t)(c * L::Q + a) * N + n] = v;
         }
 }
