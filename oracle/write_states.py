@@ -134,6 +134,39 @@ def e7_state():
             "eos": "PR", "T_scale_per_K": sT, "p_scale_per_bar": sP, "state": _state(fr)}
 
 
+def envelope_states():
+    """Sec. IV.B: C2/nC5 with PR; p-x points on the isotherms 274.96 K and
+    387.70 K, T-x points on the isobars 30, 45 and 58 bar, each at the feed
+    that gives S_V = 0.5 (the phase compositions of a binary at fixed T and p
+    do not depend on the feed)."""
+    Tc, Pc, om, M, sT, sP = th.physical_to_lattice(["C2", "nC5"], "PR")
+    kappa = [0.1, 0.2]
+
+    def point(T_K, p_bar):
+        mix = th.Mixture(Tc, Pc, om, T_K * sT, eos="PR", R=1.0, M=M, kappa=np.array(kappa))
+        for z1 in np.linspace(0.02, 0.98, 49):
+            fr = th.flash(mix, [z1, 1 - z1], p_bar * sP)
+            if fr.two_phase:
+                break
+        assert fr.two_phase, (T_K, p_bar)
+        beta = fr.vL / (fr.vL + fr.vV)          # vapor mole fraction at S_V = 0.5
+        z1 = beta * fr.y[0] + (1 - beta) * fr.x[0]
+        return {"T_K": T_K, "p_bar": p_bar, "T": float(mix.T), "p": float(fr.p), "x1": float(fr.x[0]),
+                "y1": float(fr.y[0]), "z1": float(z1), "rho_L": fr.rho_i_L.tolist(), "rho_V": fr.rho_i_V.tolist()}
+
+    curves = [
+        {"kind": "isotherm", "T_K": 274.96, "points": [point(274.96, p) for p in (4.0, 8.0, 12.0, 16.0, 20.0, 23.0)]},
+        {"kind": "isotherm", "T_K": 387.70, "points": [point(387.70, p) for p in (10.0, 20.0, 30.0, 40.0, 50.0, 60.0)]},
+        {"kind": "isobar", "p_bar": 30.0, "points": [point(T, 30.0) for T in (290.0, 325.0, 360.0, 395.0, 430.0, 455.0)]},
+        {"kind": "isobar", "p_bar": 45.0, "points": [point(T, 45.0) for T in (310.0, 340.0, 370.0, 400.0, 430.0, 448.0)]},
+        {"kind": "isobar", "p_bar": 58.0, "points": [point(T, 58.0) for T in (330.0, 350.0, 370.0, 390.0, 410.0, 422.0)]},
+    ]
+    comps = [{"Tc": float(Tc[i]), "Pc": float(Pc[i]), "omega": float(om[i]), "M": float(M[i]),
+              "kappa": kappa[i]} for i in range(2)]
+    return {"components": comps, "kij": np.zeros((2, 2)).tolist(), "eos": "PR", "T_scale_per_K": sT,
+            "p_scale_per_bar": sP, "curves": curves}
+
+
 def main():
     out = {"_note": "written by oracle/write_states.py; lattice units, R = 1"}
     # binary, T = 0.8 Tc2; z1 = 0.3 at S_V = 0.5 (the literal z1 = 0.5 has no
@@ -166,6 +199,7 @@ def main():
     out["e5_c1c2c3"] = e5_state()
     out["e6_c2c5_spinodal"] = e6_state()
     out["e7_c3c5_droplet"] = e7_state()
+    out["e2e3_c2c5_envelopes"] = envelope_states()
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)

@@ -78,14 +78,6 @@ __device__ __forceinline__ int node_index(int xcd_chunk, int N, bool rev = false
     return (lb < 0 || n >= N) ? -1 : n;
 }
 
-template <typename P>
-__device__ __forceinline__ void store_pop(P* p, P v, bool nt) {
-    if (nt)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
-
 // Lattice extent (per solver, or per request in the batched server).
 struct Dims {
     int nx, ny, nz, N;

@@ -134,6 +134,27 @@ WORKLOADS = {
 }
 
 
+# Sec. IV.B p-x and T-x envelopes: C2/nC5 (PR), D2Q9 200 x 2, tau = 1.25,
+# kappa = (0.1, 0.2), W = 4, S_V = 0.5, 5e5 steps per point; the points (T, p
+# and flash phase densities) are in the states file
+ENVELOPE = dict(state_key="e2e3_c2c5_envelopes", shape=(200, 2), tau=1.25, W=4.0, SV=0.5, steps=500000)
+
+
+def envelope_curves():
+    """(components, curves): the curves' points with T, p (lattice units and
+    K, bar) and the flash phase densities."""
+    st = states()[ENVELOPE["state_key"]]
+    return [dict(c) for c in st["components"]], st["curves"]
+
+
+def envelope_field(point):
+    """eq. eqInit slab of one envelope point, [2, 1, ny, nx]."""
+    nx, ny = ENVELOPE["shape"]
+    x = np.broadcast_to(np.arange(nx, dtype=np.float64), (1, ny, nx))
+    return np.ascontiguousarray(np.stack([slab_profile(x, nx, point["rho_L"][i], point["rho_V"][i],
+                                                       ENVELOPE["SV"], ENVELOPE["W"]) for i in range(2)]))
+
+
 def _grid(shape):
     """Node coordinates (0-based node index, x fastest), each of shape [nz, ny, nx]."""
     nx, ny = shape[0], shape[1]

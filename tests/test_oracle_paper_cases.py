@@ -159,3 +159,49 @@ def test_e6_uniform_start_is_inside_the_spinodal():
     assert abs(J[0, 1] - J[1, 0]) < 1e-6 * abs(J).max()   # a Hessian: symmetric
     assert np.linalg.eigvalsh(0.5 * (J + J.T)).min() < 0
 
+
+
+# -------------------------------------------------------- Sec. IV.B, E2/E3
+def _env_mix(comps, T):
+    return th.Mixture([c["Tc"] for c in comps], [c["Pc"] for c in comps], [c["omega"] for c in comps], T,
+                      eos="PR", R=1.0, M=[c["M"] for c in comps])
+
+
+def test_envelope_points_are_two_phase_at_half_saturation():
+    comps, curves = wl.envelope_curves()
+    for curve in curves:
+        for pt in curve["points"]:
+            mix = _env_mix(comps, pt["T"])
+            fr = th.flash(mix, [pt["z1"], 1 - pt["z1"]], pt["p"])
+            assert fr.two_phase
+            assert abs(fr.SV - 0.5) < 1e-9
+            assert abs(fr.x[0] - pt["x1"]) < 1e-10 and abs(fr.y[0] - pt["y1"]) < 1e-10
+
+
+def test_isotherm_ends_at_pure_saturation_pressures():
+    """At 274.96 K (below both critical temperatures) the p-x envelope runs
+    from x_C2 = 0 at nC5's saturation pressure to x_C2 = 1 at C2's; at 387.70 K
+    (above C2's Tc) it closes before x_C2 = 1 (Sec. IV.B).  Pure saturation
+    pressures by Maxwell's equal-area construction, no fugacity used."""
+    comps, curves = wl.envelope_curves()
+    sT = wl.states()["e2e3_c2c5_envelopes"]["T_scale_per_K"]
+    T1 = 274.96 * sT
+    pure = lambda i, T: th.Mixture([comps[i]["Tc"]], [comps[i]["Pc"]], [comps[i]["omega"]], T, eos="PR", R=1.0)
+    p_c2 = th.maxwell_equal_area(pure(0, T1))[0]
+    p_c5 = th.maxwell_equal_area(pure(1, T1))[0]
+    mix = _env_mix(comps, T1)
+    def two_phase_near(p, feeds):
+        for z in feeds:        # the two-phase window is narrow next to a pure end
+            fr = th.flash(mix, [z, 1 - z], p)
+            if fr.two_phase:
+                return fr
+        raise AssertionError("no two-phase feed")
+    hi = two_phase_near(p_c2 * (1 - 2e-3), 1 - np.geomspace(1e-4, 1e-1, 40))
+    lo = two_phase_near(p_c5 * (1 + 2e-3), np.geomspace(1e-4, 1e-1, 40))
+    assert hi.x[0] > 0.99 and lo.x[0] < 0.01
+    assert not th.flash(mix, [0.5, 0.5], p_c2 * 1.01).two_phase   # above the envelope
+    T2 = 387.70 * sT
+    assert T2 > comps[0]["Tc"]
+    mix2 = _env_mix(comps, T2)
+    xs = [th.flash(mix2, [z, 1 - z], p) for p in np.linspace(0.01, 0.085, 60) for z in (0.3, 0.6)]
+    assert max(fr.x[0] for fr in xs if fr.two_phase) < 0.8
