@@ -1,11 +1,15 @@
 // HIP kernels of the per-step update and its auxiliary passes (gfx950).
 //
 // Layout in HBM (structure of arrays, node index n = x + nx*(y + ny*z)):
-//   populations  g[a][n][c]   direction-major, the N_c components of one
-//                             direction of one node side by side (one vector
-//                             load or store per direction and node); P = double,
-//                             or float in the FP32 form where the rest slot
-//                             a = 0 holds g_0 minus rref[n][c]
+//   populations  g[a][n][c] for N_c <= 2: direction-major, the components of
+//                             one direction of one node side by side (one
+//                             vector load and one vector push store per
+//                             direction and node);
+//                g[c][a][n] for N_c >= 3: component-major (each component
+//                             stored right after its collision: register
+//                             pressure), see pop_base / pop_off;
+//                             P = double, or float in the FP32 form where the
+//                             rest slot a = 0 holds g_0 minus rref[n][c]
 //   rt[c][n], lnf[c][n]       molar densities and ln f of the current step (FP64);
 //                             plane c = N_c of lnf holds phi[n] = sum_j sqrt(kappa_j) rho~_j
 //   fsum[n][k]                sum_i F_i of the previous step (population precision;
@@ -32,19 +36,34 @@ __device__ __forceinline__ void st(T* base, unsigned byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
-// Start of direction a's block of N nodes x N_c components.
+// Population (c, a) of node n sits at pop_base(g, c, a) + pop_off(n): a
+// wave-uniform base and a 32-bit per-node byte offset.
+template <int NC>
+constexpr bool kInterleaved = NC <= 2;
+template <int NC, int Q, typename P>
+__device__ __forceinline__ const P* pop_base(const P* g, int c, int a, size_t N) {
+    return kInterleaved<NC> ? g + (size_t)a * N * NC + c : g + (size_t)(c * Q + a) * N;
+}
+template <int NC, int Q, typename P>
+__device__ __forceinline__ P* pop_base(P* g, int c, int a, size_t N) {
+    return kInterleaved<NC> ? g + (size_t)a * N * NC + c : g + (size_t)(c * Q + a) * N;
+}
 template <int NC, typename P>
-__device__ __forceinline__ const P* dir_base(const P* g, int a, size_t N) { return g + (size_t)a * N * NC; }
-template <int NC, typename P>
-__device__ __forceinline__ P* dir_base(P* g, int a, size_t N) { return g + (size_t)a * N * NC; }
+__device__ __forceinline__ unsigned pop_off(int n) {
+    return (unsigned)n * (unsigned)((kInterleaved<NC> ? NC : 1) * sizeof(P));
+}
+template <int NC, int Q>
+__device__ __forceinline__ size_t pop_index(int c, int a, size_t n, size_t N) {
+    return kInterleaved<NC> ? ((size_t)a * N + n) * NC + c : ((size_t)c * Q + a) * N + n;
+}
 
 template <typename L, int NC, typename P>
 __device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t N, P (&gv)[NC][L::Q]) {
-    const unsigned off = (unsigned)n * (unsigned)(NC * sizeof(P));
+    const unsigned off = pop_off<NC, P>(n);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) gv[c][a] = ld(dir_base<NC>(g, a, N), off + c * (unsigned)sizeof(P));
+        for (int c = 0; c < NC; ++c) gv[c][a] = ld(pop_base<NC, L::Q>(g, c, a, N), off);
 }
 
 // rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
@@ -220,18 +239,18 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         if (dx) m += step[0][dx > 0];
         if (dy) m += step[1][dy > 0];
         if (D == 3 && dz) m += step[2][dz > 0];
-        return (unsigned)m * (unsigned)(NC * sizeof(P));   // byte offset of node m's components
+        return pop_off<NC, P>(m);   // byte offset of node m's populations
     };
 
     P gv[NC][Q];
     if constexpr (NTLD) {
-        const unsigned off = (unsigned)n * (unsigned)(NC * sizeof(P));
+        const unsigned off = pop_off<NC, P>(n);
 #pragma unroll
         for (int a = 0; a < Q; ++a)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 gv[c][a] = __builtin_nontemporal_load(reinterpret_cast<const P*>(
-                    reinterpret_cast<const char*>(dir_base<NC>(g, a, N)) + off + c * sizeof(P)));
+                    reinterpret_cast<const char*>(pop_base<NC, Q>(g, c, a, N)) + off));
     } else {
         load_pops<L, NC, P>(g, n, N, gv);
     }
@@ -254,17 +273,16 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         const double fk = kp.force_level ? Fs[k] : (double)ld(fsum_in, ((unsigned)n * D + k) * (unsigned)sizeof(P));
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
-    // Push: direction a goes to n + e_a.  With two components both values of a
-    // direction leave as one vector store (all outputs live at once); with
-    // more, each component is stored right after its collision (register
-    // pressure), and L2 merges the interleaved partial lines.
-    constexpr bool kJoint = NC <= 2;
+    // Push: direction a goes to n + e_a.  With the interleaved layout (N_c <= 2)
+    // both values of a direction leave as one vector store (all outputs live
+    // at once); with more components each is stored right after its collision.
+    constexpr bool kJoint = kInterleaved<NC>;
     T out[kJoint ? NC : 1][Q];
     auto push = [&](int c, const T (&o)[Q]) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-            P* dst = dir_base<NC>(gn, a, N);
-            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]) + c * (unsigned)sizeof(P);
+            P* dst = pop_base<NC, Q>(gn, c, a, N);
+            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]);
             if (nt)
                 __builtin_nontemporal_store(o[a], (P*)((char*)dst + off));
             else
@@ -297,7 +315,7 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
             V v;
 #pragma unroll
             for (int c = 0; c < NC; ++c) v[c] = out[c][a];
-            V* dst = reinterpret_cast<V*>(reinterpret_cast<char*>(dir_base<NC>(gn, a, N)) +
+            V* dst = reinterpret_cast<V*>(reinterpret_cast<char*>(pop_base<NC, Q>(gn, 0, a, N)) +
                                           nbr_off(L::ex[a], L::ey[a], L::ez[a]));
             if (nt)
                 __builtin_nontemporal_store(v, dst);
@@ -538,7 +556,7 @@ __global__ __launch_bounds__(256) void k_init(KParams kp, const double* __restri
                 ge += L::w[a] * rho;  // standard equilibrium w_a rho (1 + ...)
             else if (a == 0)
                 ge += rho - ref;
-            g[((size_t)a * N + n) * NC + c] = (P)ge;
+            g[pop_index<NC, Q>(c, a, n, N)] = (P)ge;
         }
     }
 #pragma unroll
@@ -595,7 +613,7 @@ __global__ __launch_bounds__(256) void k_export_pops(KParams kp, const P* __rest
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int a = 0; a < L::Q; ++a) {
-            double v = (double)g[((size_t)a * N + n) * NC + c];
+            double v = (double)g[pop_index<NC, L::Q>(c, a, n, N)];
             if constexpr (sizeof(P) == 4)
                 if (a == 0) v += (double)rref[(size_t)n * NC + c];
             out[(size_t)(c * L::Q + a) * N + n] = v;

@@ -13,8 +13,8 @@ struct LaunchCfg {
     int precision;  // 0 FP64, 1 FP32 populations
     bool mrt;
     hipStream_t stream;
-    int block_k1 = 256;     // threads per block of the moments/EOS kernel
-    int block_k2 = 64;      // threads per block of the collide/stream kernel
+    int block_k1 = 128;     // threads per block of the moments/EOS kernel
+    int block_k2 = 128;     // threads per block of the collide/stream kernel
     bool xcd_remap = true;  // XCD-contiguous block order
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
