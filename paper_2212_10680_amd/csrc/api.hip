@@ -229,6 +229,7 @@ int setup(fl_solver* s, const fl_params* p) {
         if ((q = std::strstr(t, "fused=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.fused = v != 0;
         if ((q = std::strstr(t, "zmarch=")) && std::sscanf(q + 7, "%d", &v) == 1) s->lc.zmarch = v != 0;
         if ((q = std::strstr(t, "rev=")) && std::sscanf(q + 4, "%d", &v) == 1) s->lc.reverse_k2 = v != 0;
+        if ((q = std::strstr(t, "order=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.slab_order = v != 0;
         if ((q = std::strstr(t, "zlen=")) && std::sscanf(q + 5, "%d", &v) == 1 && v >= 1 && v <= 4096)
             s->lc.zlen = v;
     }

@@ -97,6 +97,25 @@ __device__ __forceinline__ int node_index(int xcd_chunk, int N, bool rev = false
     return (lb < 0 || n >= N) ? -1 : n;
 }
 
+// Visiting order of the nodes: the k-th node visited is slab_order(k).  The
+// x-lines (rows) of the lattice are taken slab by slab, zs planes per slab,
+// and y-major inside a slab (z fastest), so the planes z +- 2 a node's stencil
+// reaches are visited together and the rows y +- 2 shortly before: the FP64
+// fields they hold are re-read from L2 instead of memory.  A bijection of
+// [0, N) for any nz, zs >= 1; zs <= 0 keeps the plain order.
+__device__ __forceinline__ int slab_order(int k, int nx, int ny, int nz, int zs) {
+    if (zs <= 0 || k < 0) return k;
+    const int x = k % nx;
+    const int r = k / nx;               // row in visiting order
+    const int per = ny * zs;            // rows per slab
+    const int sl = r / per;
+    const int p = r - sl * per;
+    const int zlen = min(zs, nz - sl * zs);
+    const int y = p / zlen;
+    const int z = sl * zs + (p - y * zlen);
+    return x + nx * (y + ny * z);
+}
+
 // Lattice extent (per solver, or per request in the batched server).
 struct Dims {
     int nx, ny, nz, N;
@@ -133,8 +152,8 @@ template <int LAT, int NC, typename P>
 __global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __restrict__ g,
                                                      const float* __restrict__ rref,
                                                      double* __restrict__ rt, double* __restrict__ lnf,
-                                                     int* __restrict__ err, int xcd_chunk) {
-    const int n = node_index(xcd_chunk, kp.N);
+                                                     int* __restrict__ err, int xcd_chunk, int zs) {
+    const int n = slab_order(node_index(xcd_chunk, kp.N), kp.nx, kp.ny, kp.nz, zs);
     if (n < 0) return;
     if (!node_moments_eos<LAT, NC, P>(kp, n, kp.N, g, rref, rt, lnf)) atomicOr(err, 1);
 }
@@ -368,8 +387,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
                                                         const P* fsum_in, P* fsum_out, int xcd_chunk, int nt,
-                                                        int rev) {
-    const int n = node_index(xcd_chunk, kp.N, rev != 0);
+                                                        int rev, int zs) {
+    const int n = slab_order(node_index(xcd_chunk, kp.N, rev != 0), kp.nx, kp.ny, kp.nz, zs);
     if (n < 0) return;
     const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
     node_collide_stream<LAT, NC, P, MRT, true>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
@@ -747,6 +766,12 @@ static inline int xcd_chunk_for(const LaunchCfg& lc, int nblocks) {
 
 static inline dim3 grid_remapped(int nblocks, int chunk) { return dim3(chunk > 0 ? 8 * chunk : nblocks); }
 
+// Planes per slab of the visiting order (slab_order): one slab per XCD on a
+// D3Q19 lattice when enabled, 0 (plain order) otherwise.
+static inline int slab_planes(const LaunchCfg& lc, const KParams& kp) {
+    return (lc.slab_order && lc.lattice == 1) ? (kp.nz + 7) / 8 : 0;
+}
+
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* rt, double* lnf, int* err) {
     const int bs = lc.block_k1;
@@ -755,7 +780,7 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         k_moments_eos<LAT, NC, P><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-            kp, (const P*)g, rref, rt, lnf, err, ch);
+            kp, (const P*)g, rref, rt, lnf, err, ch, slab_planes(lc, kp));
     });
     return hipGetLastError();
 }
@@ -772,10 +797,12 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
         FL_TYPES;
         if (lc.mrt)
             k_collide_stream<LAT, NC, P, true><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
+                slab_planes(lc, kp));
         else
             k_collide_stream<LAT, NC, P, false><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev);
+                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
+                slab_planes(lc, kp));
     });
     return hipGetLastError();
 }

@@ -121,8 +121,9 @@ def test_bench_lattices_zmarch_equals_plain(wname):
     ("ternary_droplets_3d", (24, 12, 7), "fp64", "MRT"),
 ])
 def test_sweep_order_bitwise(wname, shape, precision, coll):
-    """The order in which the collide/stream pass visits the nodes (forward or
-    reversed, XCD-contiguous or plain block order) changes no bit."""
+    """The order in which the passes visit the nodes (forward or reversed,
+    XCD-contiguous or plain block order, plane-major or y-major inside z-slabs,
+    any block size) changes no bit."""
     w = wl.WORKLOADS[wname].scaled(shape)
     w.collision = coll
     w.u0 = 0.0
@@ -131,7 +132,8 @@ def test_sweep_order_bitwise(wname, shape, precision, coll):
     announce(f"sweep order {wname} {shape} {precision} {coll}")
     rho, u = smooth_3d_field(w, amp=0.005)
     ref = None
-    for tune in ("rev=0,remap=1", "rev=1,remap=1", "rev=1,remap=0", "rev=0,remap=0"):
+    for tune in ("rev=0,remap=1", "rev=1,remap=1", "rev=1,remap=0", "rev=0,remap=0",
+                 "order=1,rev=1", "order=1,rev=0,remap=0", "order=1,k1block=64,k2block=256"):
         s = solver(w, precision, tune)
         s.set_state(rho, u)
         s.step(15)
