@@ -224,7 +224,8 @@ int fl_server_submit(fl_server* srv, int nx, int ny, int nz, const double* rho_m
 
 /* One tick (synchronous): every running request advances by up to `steps`
  * steps, and stops early once max_ms milliseconds of device time have passed
- * since its workgroup started (max_ms <= 0: no time limit), so that large and
+ * since its workgroup started (checked every 8 steps, so a request may run up
+ * to 8 steps past the limit; max_ms <= 0: no time limit), so that large and
  * small requests leave the tick together.  *active receives the requests still
  * running. */
 int fl_server_tick(fl_server* srv, long steps, double max_ms, int* active);

@@ -1053,13 +1053,14 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
             status = kSlotMaxSteps;
             break;
         }
-        if (clock_budget > 0) {
-            // time slice: every thread sees the same decision
+        if (clock_budget > 0 && (s & 7) == 0) {
+            // time slice, decided every 8 steps (a slice overruns its budget by
+            // at most 8 steps); every thread sees the same decision.  The next
+            // write of s_go is 8 steps and at least 16 barriers later, so no
+            // second barrier is needed before it.
             if (threadIdx.x == 0) s_go = (long long)(wall_clock64() - s_t0) < clock_budget;
             __syncthreads();
-            const int go = s_go;
-            __syncthreads();
-            if (!go) break;
+            if (!s_go) break;
         }
         bool ok = true;
         for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
