@@ -205,13 +205,15 @@ def main():
     ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
                     help="uniform: the workload's mean composition everywhere (a steady state; the "
                          "per-step work does not depend on the state)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="print the attainable HBM rates of the kernels' access patterns and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (PMC byte-counter scale)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; runs on more than one GPU are not part of it",
-              file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (the multi-GPU decomposition is a design, not "
+              "an implementation); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -219,6 +221,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.stream_probe:
+        import ctypes
+        from paper_2212_10680_amd import build as B
+        if not os.path.exists(B.PROBE_LIB):
+            raise ImportError(f"{B.PROBE_LIB} is not built: run python -m paper_2212_10680_amd.build")
+        lib = ctypes.CDLL(B.PROBE_LIB)
+        buf = ctypes.create_string_buffer(1 << 14)
+        rc = lib.flp_stream_probe(buf, len(buf))
+        print(buf.value.decode(), end="")
+        sys.exit(0 if rc == 0 else 1)
     F.load()  # fails loudly when the HIP library is not built
 
     w = wl.WORKLOADS[args.workload]

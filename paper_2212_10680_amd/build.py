@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfuglbm.so")
+PROBE_LIB = os.path.join(HERE, "libflprobe.so")
 SOURCES = ["kernels.hip", "api.hip"]
 
 HIPCC_FLAGS = [
@@ -53,7 +54,20 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(hc, verbose)
     return LIB
+
+
+def build_probe(hc, verbose=False):
+    """The bandwidth probe the benchmark reports its ceilings with
+    (``bench.py --stream-probe``); a library of its own, not the solver's."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hc, *HIPCC_FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, "probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
