@@ -214,6 +214,10 @@ int setup(fl_solver* s, const fl_params* p) {
     // memory-side cache: each pass then starts on the lines the other touched
     // last.  Larger lattices gain nothing from it.
     s->lc.reverse_k2 = (double)s->nc * s->Q * s->N * s->pop_elem <= 1073741824.0;
+    // The z-marching collide kernel (stencil fields staged through LDS) is the
+    // faster one with one or two components; with three its registers cost
+    // more than the re-reads it saves (measured on the 256^3 ternary lattice).
+    s->lc.zmarch = p->ncomp <= 2;
     // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0,rev=1,zmarch=0,zlen=16"
     if (const char* t = std::getenv("FUGLBM_TUNE")) {
         int v;

@@ -415,7 +415,7 @@ constexpr int kRlPts = kRlW * kRlH;
 constexpr int kPhiPer = (kPhiPts + 255) / 256;   // fill points per thread
 constexpr int kRlPer = (kRlPts + 255) / 256;
 
-template <int NC, typename P, bool MRT>
+template <int NC, typename P, bool MRT, int DIR>
 __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __restrict__ g,
                                                         P* __restrict__ gn,
                                                         const float* __restrict__ rref,
@@ -423,6 +423,11 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
                                                         const double* __restrict__ lnf,
                                                         const P* fsum_in, P* fsum_out, int zlen, int xcd_chunk,
                                                         int nt) {
+    // DIR = +1 marches each z-range upward, -1 downward (and takes an XCD's
+    // z-ranges top-down), so that a pass following one sweep starts where that
+    // sweep ended.  All ring bookkeeping is relative to the march direction:
+    // "ahead" is z + DIR.
+    static_assert(DIR == 1 || DIR == -1, "march direction");
     const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
     const size_t N = kp.N;
     const int plane = nx * ny;
@@ -430,11 +435,13 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
     const int tiles_xy = tiles_x * (ny / kZY);
     const int nzc = (nz + zlen - 1) / zlen;
     const int b = blockIdx.x;
-    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    const int j = b >> 3;
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (DIR > 0 ? j : xcd_chunk - 1 - j) : b;
     if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
     const int zc = lb / tiles_xy, txy = lb - zc * tiles_xy;
     const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
+    const int start = DIR > 0 ? z0 : z1 - 1;
     const int t = threadIdx.x;
     const int tx = t % kZX, ty = t / kZX;
     const int x = x0 + tx, y = y0 + ty;
@@ -465,56 +472,62 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
     auto rl_src = [&](int f) { return f < NC ? rt + (size_t)f * N : lnf + (size_t)(f - NC) * N; };
     const unsigned col8 = 8u * (unsigned)col;
 
-    // prologue: phi planes z0-1, z0, z0+1 -> slots 0, 1, 2; rt/ln f plane z0 -> slot 0
+    // prologue: phi planes start - DIR, start, start + DIR -> slots 0, 1, 2;
+    // rt / ln f plane start -> slot 0; the own column's planes behind in registers
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double* src = phig + zoff(z0 - 1 + d);
+        const double* src = phig + zoff(start + (d - 1) * DIR);
 #pragma unroll
         for (int k = 0; k < kPhiPer; ++k)
             if (phi_fills(k)) s_phi[d][t + 256 * k] = ld(src, phi_off[k]);
     }
 #pragma unroll
     for (int f = 0; f < 2 * NC; ++f) {
-        const double* src = rl_src(f) + zoff(z0);
+        const double* src = rl_src(f) + zoff(start);
 #pragma unroll
         for (int k = 0; k < kRlPer; ++k)
             if (rl_fills(k)) s_rl[0][f][t + 256 * k] = ld(src, rl_off[k]);
     }
-    double phi_m2 = ld(phig + zoff(z0 - 2), col8);
-    double phi_m1 = ld(phig + zoff(z0 - 1), col8);
-    double rl_m1[2 * NC];
+    double phi_b2 = ld(phig + zoff(start - 2 * DIR), col8);
+    double phi_b1 = ld(phig + zoff(start - DIR), col8);
+    double rl_b1[2 * NC];
 #pragma unroll
-    for (int f = 0; f < 2 * NC; ++f) rl_m1[f] = ld(rl_src(f) + zoff(z0 - 1), col8);
+    for (int f = 0; f < 2 * NC; ++f) rl_b1[f] = ld(rl_src(f) + zoff(start - DIR), col8);
     __syncthreads();
 
     const int cphi = (ty + 2) * kPhiW + tx + 2;  // this node in the phi tile
     const int crl = (ty + 1) * kRlW + tx + 1;    // this node in the rt / ln f tile
-    for (int zz = z0, it = 0; zz < z1; ++zz, ++it) {
+    for (int it = 0; it < z1 - z0; ++it) {
+        const int zz = start + it * DIR;
         // loads of the planes being filled (written to LDS after the node's work)
         double fphi[kPhiPer], frl[2 * NC][kRlPer];
-        const double* phi2 = phig + zoff(zz + 2);
+        const double* phi2 = phig + zoff(zz + 2 * DIR);
 #pragma unroll
         for (int k = 0; k < kPhiPer; ++k) fphi[k] = ld(phi2, phi_off[k]);
-        const size_t z1off = zoff(zz + 1);
+        const size_t a1off = zoff(zz + DIR);
 #pragma unroll
         for (int f = 0; f < 2 * NC; ++f)
 #pragma unroll
-            for (int k = 0; k < kRlPer; ++k) frl[f][k] = ld(rl_src(f) + z1off, rl_off[k]);
-        const double phi_p2 = ld(phi2, col8);
-        double rl_p1[2 * NC];
+            for (int k = 0; k < kRlPer; ++k) frl[f][k] = ld(rl_src(f) + a1off, rl_off[k]);
+        const double phi_a2 = ld(phi2, col8);
+        double rl_a1[2 * NC];
 #pragma unroll
-        for (int f = 0; f < 2 * NC; ++f) rl_p1[f] = ld(rl_src(f) + z1off, col8);
+        for (int f = 0; f < 2 * NC; ++f) rl_a1[f] = ld(rl_src(f) + a1off, col8);
 
-        const int s0 = (it + 1) & 3;  // phi slot of plane zz (plane z0-1+j lives in slot j&3)
-        const int r0 = it & 1;        // rt / ln f slot of plane zz
+        // plane start + (j - 1) DIR lives in phi slot j & 3, plane start + j DIR
+        // in rt / ln f slot j & 1
+        const int s0 = (it + 1) & 3;
+        const int r0 = it & 1;
         auto phi_at = [&](int dx, int dy, int dz) -> double {
-            if (dz == -2) return phi_m2;
-            if (dz == 2) return phi_p2;
-            return s_phi[(s0 + dz) & 3][cphi + dy * kPhiW + dx];
+            const int d = dz * DIR;  // offset along the march
+            if (d == -2) return phi_b2;
+            if (d == 2) return phi_a2;
+            return s_phi[(s0 + d) & 3][cphi + dy * kPhiW + dx];
         };
         auto rl_at = [&](int f, int dx, int dy, int dz) -> double {
-            if (dz == -1) return rl_m1[f];
-            if (dz == 1) return rl_p1[f];
+            const int d = dz * DIR;
+            if (d == -1) return rl_b1[f];
+            if (d == 1) return rl_a1[f];
             return s_rl[r0][f][crl + dy * kRlW + dx];
         };
         P F[NC][3], G[NC][3];
@@ -526,10 +539,10 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
                                           fsum_out, nt != 0);
 
         // shift the own-column registers, store the filled planes, publish
-        phi_m2 = phi_m1;
-        phi_m1 = s_phi[s0][cphi];
+        phi_b2 = phi_b1;
+        phi_b1 = s_phi[s0][cphi];
 #pragma unroll
-        for (int f = 0; f < 2 * NC; ++f) rl_m1[f] = s_rl[r0][f][crl];
+        for (int f = 0; f < 2 * NC; ++f) rl_b1[f] = s_rl[r0][f][crl];
 #pragma unroll
         for (int k = 0; k < kPhiPer; ++k)
             if (phi_fills(k)) s_phi[(it + 3) & 3][t + 256 * k] = fphi[k];
@@ -821,12 +834,20 @@ hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const v
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         if constexpr (LAT == 1 && NC <= 3) {
-            if (lc.mrt)
-                k_collide_zmarch<NC, P, true><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
-                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
-            else
-                k_collide_zmarch<NC, P, false><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
-                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+            // march downward when the passes alternate direction (reverse_k2)
+            auto go = [&](auto mrt, auto dir) {
+                k_collide_zmarch<NC, P, decltype(mrt)::value, decltype(dir)::value>
+                    <<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf,
+                                                                   (const P*)fsum_in, (P*)fsum_out, lc.zlen,
+                                                                   ch, nt);
+            };
+            using Up = std::integral_constant<int, 1>;
+            using Down = std::integral_constant<int, -1>;
+            if (lc.mrt) {
+                if (lc.reverse_k2) go(std::true_type{}, Down{}); else go(std::true_type{}, Up{});
+            } else {
+                if (lc.reverse_k2) go(std::false_type{}, Down{}); else go(std::false_type{}, Up{});
+            }
         }
     });
     return hipGetLastError();

@@ -19,7 +19,7 @@ struct LaunchCfg {
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
     bool fused = false;     // one-launch step (FUGLBM_TUNE fused=1) when the lattice allows it
-    bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (FUGLBM_TUNE zmarch=1)
+    bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (set per solver)
     bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
     bool slab_order = false;  // y-major row order inside per-XCD z-slabs (FUGLBM_TUNE order=1)
     int zlen = 16;          // planes per workgroup of the z-marching kernel

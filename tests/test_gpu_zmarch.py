@@ -48,17 +48,20 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("rev", [0, 1])
 @pytest.mark.parametrize("wname,shape,precision,coll,zlen", CASES)
-def test_zmarch_equals_plain_bitwise(wname, shape, precision, coll, zlen):
+def test_zmarch_equals_plain_bitwise(wname, shape, precision, coll, zlen, rev):
+    """rev = 1 marches each z-range downward (the default when the passes
+    alternate direction), rev = 0 upward."""
     w = wl.WORKLOADS[wname].scaled(shape)
     w.collision = coll
     w.u0 = 0.0
     if w.geometry == "two_droplets":
         w.geometry = "slab"
-    announce(f"zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen}")
+    announce(f"zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen} rev={rev}")
     rho, u = smooth_3d_field(w, amp=0.005)
-    a = solver(w, precision, f"zmarch=1,zlen={zlen}")
-    b = solver(w, precision, "zmarch=0")
+    a = solver(w, precision, f"zmarch=1,zlen={zlen},rev={rev}")
+    b = solver(w, precision, f"zmarch=0,rev={rev}")
     a.set_state(rho, u)
     b.set_state(rho, u)
     assert list(a.step_timed(2)) == ["k_moments_eos", "k_collide_zmarch"]
@@ -97,7 +100,7 @@ def test_zmarch_fp64_vs_oracle():
 def test_bench_lattices_zmarch_equals_plain(wname):
     """The benchmark lattices at full size (D3Q19 128^3 binary BGK and 256^3
     ternary MRT, FP32 populations): the z-marching kernel bitwise equal to the
-    plain one (default launch configuration) after a few steps."""
+    plain one after a few steps."""
     w = wl.WORKLOADS[wname]
     announce(f"bench lattice {wname} {w.shape}")
     rho, u = wl.initial_field(w)
@@ -109,7 +112,7 @@ def test_bench_lattices_zmarch_equals_plain(wname):
     fa = a.fields()["rho_molar"]
     a.close()
     del a
-    b = solver(w, "fp32", "")
+    b = solver(w, "fp32", "zmarch=0")
     b.set_state(rho, u)
     assert list(b.step_timed(1)) == ["k_moments_eos", "k_collide_stream"]
     b.step(steps - 1)

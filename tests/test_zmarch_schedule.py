@@ -1,7 +1,7 @@
 """CPU replay of the z-marching collide/stream kernel's data staging.
 
 The kernel (k_collide_zmarch) gives each 256-thread workgroup a 64 x 4 tile of
-(x, y) and a range of z planes, keeps phi in a 4-slot LDS ring (tile + halo 2),
+(x, y) and a range of z planes, marched upward or downward, keeps phi in a 4-slot LDS ring (tile + halo 2),
 rt and ln f in a 2-slot ring (tile + halo 1), and the node's own column at
 z +- 1, z +- 2 in registers or fresh loads.  This replays that schedule with
 the kernel's index arithmetic (fill offsets, slot numbers, register shifts,
@@ -30,7 +30,7 @@ def wrap2(v, m):
     return np.where(v >= m, v - m, v)
 
 
-def replay(nx, ny, nz, zlen, remap=True):
+def replay(nx, ny, nz, zlen, remap=True, direction=1):
     rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
     phi = rng.standard_normal((nz, ny, nx))
     rl = rng.standard_normal((nz, ny, nx))   # one rt / ln f field stands for all
@@ -46,14 +46,17 @@ def replay(nx, ny, nz, zlen, remap=True):
     t = np.arange(256)
     tx, ty = t % ZX, t // ZX
     visits = np.zeros((nz, ny, nx), dtype=int)
+    D = direction
     for b in range(grid):
-        lb = (b & 7) * chunk + (b >> 3) if remap else b
+        j = b >> 3
+        lb = (b & 7) * chunk + (j if D > 0 else chunk - 1 - j) if remap else b
         if lb >= nb:
             continue
         seen.append(lb)
         zc, txy = lb // tiles_xy, lb % tiles_xy
         x0, y0 = (txy % tiles_x) * ZX, (txy // tiles_x) * ZY
         z0, z1 = zc * zlen, min(zc * zlen + zlen, nz)
+        start = z0 if D > 0 else z1 - 1
         x, y = x0 + tx, y0 + ty
         col = x + nx * y
         phi_off, rl_off = [], []
@@ -82,35 +85,38 @@ def replay(nx, ny, nz, zlen, remap=True):
                 dst[slot, idx] = src[o[m]]
 
         for d in range(3):
-            fill(s_phi, d, flat_phi[zoff(z0 - 1 + d):], phi_off)
-        fill(s_rl, 0, flat_rl[zoff(z0):], rl_off)
-        phi_m2 = flat_phi[zoff(z0 - 2) + col]
-        phi_m1 = flat_phi[zoff(z0 - 1) + col]
-        rl_m1 = flat_rl[zoff(z0 - 1) + col]
+            fill(s_phi, d, flat_phi[zoff(start + (d - 1) * D):], phi_off)
+        fill(s_rl, 0, flat_rl[zoff(start):], rl_off)
+        phi_b2 = flat_phi[zoff(start - 2 * D) + col]
+        phi_b1 = flat_phi[zoff(start - D) + col]
+        rl_b1 = flat_rl[zoff(start - D) + col]
         cphi = (ty + 2) * PHI_W + tx + 2
         crl = (ty + 1) * RL_W + tx + 1
-        for it, zz in enumerate(range(z0, z1)):
-            fphi = [np.where(o >= 0, flat_phi[zoff(zz + 2) + np.maximum(o, 0)], 0.0) for o in phi_off]
-            frl = [np.where(o >= 0, flat_rl[zoff(zz + 1) + np.maximum(o, 0)], 0.0) for o in rl_off]
-            phi_p2 = flat_phi[zoff(zz + 2) + col]
-            rl_p1 = flat_rl[zoff(zz + 1) + col]
+        for it in range(z1 - z0):
+            zz = start + it * D
+            fphi = [np.where(o >= 0, flat_phi[zoff(zz + 2 * D) + np.maximum(o, 0)], 0.0) for o in phi_off]
+            frl = [np.where(o >= 0, flat_rl[zoff(zz + D) + np.maximum(o, 0)], 0.0) for o in rl_off]
+            phi_a2 = flat_phi[zoff(zz + 2 * D) + col]
+            rl_a1 = flat_rl[zoff(zz + D) + col]
             s0, r0 = (it + 1) & 3, it & 1
             for dx, dy, dz in PHI_OFFS:
-                if dz == -2:
-                    got = phi_m2
-                elif dz == 2:
-                    got = phi_p2
+                d = dz * D
+                if d == -2:
+                    got = phi_b2
+                elif d == 2:
+                    got = phi_a2
                 else:
                     i = cphi + dy * PHI_W + dx
                     assert i.min() >= 0 and i.max() < PHI_PTS
-                    got = s_phi[(s0 + dz) & 3, i]
+                    got = s_phi[(s0 + d) & 3, i]
                 want = phi[wrap2(zz + dz, nz), wrap2(y + dy, ny), wrap2(x + dx, nx)]
                 np.testing.assert_array_equal(got, want, err_msg=f"phi {dx, dy, dz} z={zz}")
             for dx, dy, dz in RL_OFFS:
-                if dz == -1:
-                    got = rl_m1
-                elif dz == 1:
-                    got = rl_p1
+                d = dz * D
+                if d == -1:
+                    got = rl_b1
+                elif d == 1:
+                    got = rl_a1
                 else:
                     i = crl + dy * RL_W + dx
                     assert i.min() >= 0 and i.max() < RL_PTS
@@ -120,8 +126,8 @@ def replay(nx, ny, nz, zlen, remap=True):
             n = col + zz * plane
             assert n.min() >= 0 and n.max() < plane * nz
             visits[zz, y, x] += 1
-            phi_m2, phi_m1 = phi_m1, s_phi[s0, cphi]
-            rl_m1 = s_rl[r0, crl]
+            phi_b2, phi_b1 = phi_b1, s_phi[s0, cphi]
+            rl_b1 = s_rl[r0, crl]
             for k in range(PHI_PER):
                 m = phi_off[k] >= 0
                 s_phi[(it + 3) & 3, (t + 256 * k)[m]] = fphi[k][m]
@@ -141,9 +147,11 @@ def replay(nx, ny, nz, zlen, remap=True):
     (128, 4, 7, 3),
     (192, 8, 6, 5),
 ])
-def test_zmarch_schedule(nx, ny, nz, zlen):
-    replay(nx, ny, nz, zlen)
+@pytest.mark.parametrize("direction", [1, -1])
+def test_zmarch_schedule(nx, ny, nz, zlen, direction):
+    replay(nx, ny, nz, zlen, direction=direction)
 
 
-def test_zmarch_schedule_no_remap():
-    replay(64, 8, 6, 4, remap=False)
+@pytest.mark.parametrize("direction", [1, -1])
+def test_zmarch_schedule_no_remap(direction):
+    replay(64, 8, 6, 4, remap=False, direction=direction)
