@@ -73,6 +73,24 @@ def bulk_values(rho):
     return rho[:, central(idx[liquid])].mean(axis=1), rho[:, central(idx[~liquid])].mean(axis=1)
 
 
+def central_pairs(rho):
+    """Like bulk_values, but the mean over the two nodes nearest the centre of
+    each region only (the narrowest even window).  Returns (rho_liquid [nc],
+    rho_vapor [nc])."""
+    rho = np.asarray(rho, dtype=np.float64)
+    tot = rho.sum(axis=0)
+    n = tot.size
+    liquid = tot > 0.5 * (tot.max() + tot.min())
+    idx = np.arange(n)
+
+    def pair(ix):
+        c = (np.angle(np.exp(2j * np.pi * ix / n).mean()) * n / (2 * np.pi)) % n
+        d = np.abs((ix - c + n / 2) % n - n / 2)
+        return ix[np.argsort(d, kind="stable")[:2]]
+
+    return rho[:, pair(idx[liquid])].mean(axis=1), rho[:, pair(idx[~liquid])].mean(axis=1)
+
+
 def flash_errors_percent(mix, z, rho_L, rho_V, names=("C3", "C5")):
     """Relative errors (eq. eqerror, in %) of bulk density and mole fractions
     against a PT flash of the feed z at the liquid bulk's EOS pressure.

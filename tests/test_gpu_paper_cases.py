@@ -39,8 +39,8 @@ from oracle import fixed_point as fp
 from paper_2212_10680_amd import fuglbm as F
 from paper_2212_10680_amd import workloads as wl
 
-from _util import (bulk_values, damped_period, direction_map, flash_errors_percent, half_width,
-                   mixture_of, oracle_for, rel, smooth_3d_field)
+from _util import (bulk_values, central_pairs, damped_period, direction_map, flash_errors_percent,
+                   half_width, mixture_of, oracle_for, rel, smooth_3d_field)
 
 pytestmark = pytest.mark.gpu
 
@@ -177,21 +177,44 @@ def test_paper_case_parity(wname, steps):
 
 
 def test_e5_reproduces_table_tabcase3():
+    """The paper's errors after 1e6 steps against the distribution of ours over
+    the 5e4 steps that follow (R-26): at 1e6 steps the liquid slab still swings
+    about a lattice-pinned position (period ~4e4 steps, |u| <= 3e-4) and the
+    bulk values move with its phase, so the printed numbers are one sample of
+    that swing.  Each must lie within 3 standard deviations of our mean, plus
+    the shift that the choice of the bulk window makes (R-17: the paper does not
+    say where it takes bulk values, and the 46-node liquid slab is not bulk at
+    its centre; measured as the mean difference between the central-quarter and
+    the central-pair averages), plus 0.005 percentage points."""
     w = wl.WORKLOADS["e5_c1c2c3"]
-    announce("E5: 1e6 steps")
+    announce("E5: 1e6 steps, then 100 samples every 500 steps")
     rho, _ = wl.initial_field(w)
     s = F.Solver(F.Params.from_workload(w, precision="fp64"))
     s.set_state(rho)
     s.step(1_000_000)
-    r = s.fields()["rho_molar"].reshape(3, 2, 200)
+    mix = mixture_of(w)
+    samples = {}
+    for i in range(100):
+        r = s.fields()["rho_molar"].reshape(3, 2, 200)
+        if i == 0:
+            assert np.array_equal(r[:, 0], r[:, 1])
+        rL, rV = bulk_values(r[:, 0])
+        errs = flash_errors_percent(mix, [0.4, 0.3, 0.3], rL, rV, names=("C1", "C2", "C3"))
+        pL, pV = central_pairs(r[:, 0])
+        errs_pair = flash_errors_percent(mix, [0.4, 0.3, 0.3], pL, pV, names=("C1", "C2", "C3"))
+        for phase, e in errs.items():
+            for k, v in e.items():
+                samples.setdefault((phase, k), []).append((v, errs_pair[phase][k]))
+        s.step(500)
     s.close()
-    assert np.array_equal(r[:, 0], r[:, 1])
-    errs = flash_errors_percent(mixture_of(w), [0.4, 0.3, 0.3], *bulk_values(r[:, 0]), names=("C1", "C2", "C3"))
-    print(f"  errors (%): {errs}", flush=True)
-    for phase in ("liquid", "vapor"):
-        for k, v in errs[phase].items():
-            tol = 0.06 if k == "density" else 0.01
-            assert abs(v - TAB3[phase][k]) <= tol, (phase, k, v, TAB3[phase][k])
+    for (phase, k), v in samples.items():
+        v = np.array(v)
+        mean, std = v[:, 0].mean(), v[:, 0].std()
+        window = abs((v[:, 1] - v[:, 0]).mean())
+        paper = TAB3[phase][k]
+        print(f"  {phase} {k}: paper {paper:.4f}, ours mean {mean:.4f} std {std:.4f} "
+              f"range [{v[:, 0].min():.4f}, {v[:, 0].max():.4f}], window shift {window:.4f}", flush=True)
+        assert abs(paper - mean) <= 3 * std + window + 0.005, (phase, k, paper, mean, std, window)
 
 
 # ------------------------------------------------------------ Sec. IV.D, E6

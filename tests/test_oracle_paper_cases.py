@@ -26,7 +26,7 @@ from oracle import fixed_point as fp
 from oracle import thermo as th
 from paper_2212_10680_amd import workloads as wl
 
-from _util import bulk_values, flash_errors_percent, mixture_of
+from _util import bulk_values, central_pairs, flash_errors_percent, mixture_of
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tabcase1error.json")))
 T_K, P_BAR, Z = 370.03, 16.547, [0.4, 0.6]
@@ -205,3 +205,21 @@ def test_isotherm_ends_at_pure_saturation_pressures():
     mix2 = _env_mix(comps, T2)
     xs = [th.flash(mix2, [z, 1 - z], p) for p in np.linspace(0.01, 0.085, 60) for z in (0.3, 0.6)]
     assert max(fr.x[0] for fr in xs if fr.two_phase) < 0.8
+
+
+@pytest.mark.parametrize("shift", [0, 37, 150])
+def test_bulk_windows_cancel_the_even_odd_mode(shift):
+    """bulk_values and central_pairs on a flat-interface profile with plateaus
+    and an even/odd alternation on top (R-18): both windows hold an even number
+    of consecutive nodes, so the alternation cancels and the plateau comes back,
+    also when a region wraps around the periodic boundary."""
+    n = 200
+    x = np.arange(n)
+    liquid = 0.5 * (np.tanh((x - 60) / 3.0) - np.tanh((x - 140) / 3.0))
+    rho = np.stack([0.3 + 4.0 * liquid, 0.1 + 1.0 * liquid])
+    rho = rho + 1e-3 * (-1.0) ** x
+    rho = np.roll(rho, shift, axis=1)
+    for fn in (bulk_values, central_pairs):
+        rL, rV = fn(rho)
+        np.testing.assert_allclose(rL, [4.3, 1.1], rtol=1e-9, err_msg=fn.__name__)
+        np.testing.assert_allclose(rV, [0.3, 0.1], rtol=1e-9, err_msg=fn.__name__)
