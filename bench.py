@@ -32,7 +32,8 @@ from paper_2212_10680_amd import workloads as wl  # noqa: E402
 METRIC = "component-MLUPS & HBM-BW fraction; batched VLE solves/s + p99 time-to-equil"
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_2212_10680_amd/csrc/kernels.hip", "paper_2212_10680_amd/csrc/device.h", "paper_2212_10680_amd/csrc/launch.h"]
+KERNEL_SOURCES = ["paper_2212_10680_amd/csrc/kernels.hip", "paper_2212_10680_amd/csrc/device.h",
+                  "paper_2212_10680_amd/csrc/launch.h", "paper_2212_10680_amd/build.py"]
 
 
 def kernel_source_hash():

@@ -20,6 +20,11 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep hipcc from forming packed FP32 instructions by itself
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b + c into an FMA only inside one source expression: which
+    # operations fuse then follows the source, not the block layout the
+    # optimiser produces, so kernels that run the same per-node functions in
+    # different loop structures give bitwise equal results
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

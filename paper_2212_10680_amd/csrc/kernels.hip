@@ -67,19 +67,34 @@ __device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t
 }
 
 // rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
+// ref[c] is the node's rest-population reference (FP32 form; unused in FP64).
 template <typename L, int NC, typename P>
-__device__ __forceinline__ void densities(const P (&gv)[NC][L::Q], const float* __restrict__ rref, int n,
-                                          size_t N, double (&rho)[NC], double (&moving)[NC]) {
+__device__ __forceinline__ void densities_ref(const P (&gv)[NC][L::Q], const float (&ref)[NC], double (&rho)[NC],
+                                              double (&moving)[NC]) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double m = 0.0;
 #pragma unroll
         for (int a = 1; a < L::Q; ++a) m += (double)gv[c][a];
         double r0 = (double)gv[c][0];
-        if constexpr (sizeof(P) == 4) r0 += (double)ld(rref, ((unsigned)n * NC + c) * 4u);
+        if constexpr (sizeof(P) == 4) r0 += (double)ref[c];
         moving[c] = m;
         rho[c] = r0 + m;
     }
+}
+
+template <int NC, typename P>
+__device__ __forceinline__ void load_ref(const float* __restrict__ rref, int n, float (&ref)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ref[c] = sizeof(P) == 4 ? ld(rref, ((unsigned)n * NC + c) * 4u) : 0.f;
+}
+
+template <typename L, int NC, typename P>
+__device__ __forceinline__ void densities(const P (&gv)[NC][L::Q], const float* __restrict__ rref, int n,
+                                          size_t N, double (&rho)[NC], double (&moving)[NC]) {
+    float ref[NC];
+    load_ref<NC, P>(rref, n, ref);
+    densities_ref<L, NC, P>(gv, ref, rho, moving);
 }
 
 // Node of this thread, or -1.  With xcd_chunk > 0 the hardware block b
@@ -232,19 +247,52 @@ __device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at,
     }
 }
 
-// Steps 8-9 (and step 1's velocity) at node n = (x, y, z): moments of the
-// node's populations, u with the force of the chosen time level, equilibrium,
-// forcing and collision per component, push streaming to n + e_a of gn.
-// With NTLD the node's populations are loaded with the non-temporal hint: each
-// is read once per pass, and keeping them out of the way leaves L2 to the FP64
-// stencil fields that neighbouring nodes re-read.
-template <int LAT, int NC, typename P, bool MRT, bool NTLD = false>
-__device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, int n, int x, int y, int z,
-                                             const P* __restrict__ g, P* __restrict__ gn,
-                                             const float* __restrict__ rref, const P (&F)[NC][3],
-                                             const P (&G)[NC][3], const double (&Fs)[3], const P* fsum_in,
-                                             P* fsum_out, bool nt) {
+// The node's own inputs of steps 8-9: its populations, its rest-population
+// reference (FP32 form) and the previous step's force sum.  With NTLD the
+// populations are loaded with the non-temporal hint: each is read once per
+// pass, and keeping them out of the way leaves L2 to the FP64 stencil fields
+// that neighbouring nodes re-read.
+template <int LAT, int NC, typename P>
+struct NodeIn {
+    P gv[NC][Lat<LAT>::Q];
+    P fprev[3];
+    float ref[NC];
+};
+
+template <int LAT, int NC, typename P, bool NTLD>
+__device__ __forceinline__ void load_node_inputs(const P* __restrict__ g, const P* fsum_in,
+                                                 const float* __restrict__ rref, int n, size_t N,
+                                                 NodeIn<LAT, NC, P>& in) {
     using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+#pragma unroll
+    for (int k = 0; k < D; ++k) in.fprev[k] = ld(fsum_in, ((unsigned)n * D + k) * (unsigned)sizeof(P));
+    if constexpr (NTLD) {
+        const unsigned off = pop_off<NC, P>(n);
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                in.gv[c][a] = __builtin_nontemporal_load(reinterpret_cast<const P*>(
+                    reinterpret_cast<const char*>(pop_base<NC, Q>(g, c, a, N)) + off));
+    } else {
+        load_pops<L, NC, P>(g, n, N, in.gv);
+    }
+    load_ref<NC, P>(rref, n, in.ref);
+}
+
+// Steps 8-9 (and step 1's velocity) at node n = (x, y, z) from its loaded
+// inputs (gv, fprev): moments of the node's populations, u with the force of
+// the chosen time level, equilibrium, forcing and collision per component, push
+// streaming to n + e_a of gn.
+template <int LAT, int NC, typename P, bool MRT>
+__device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dims& dm, int n, int x, int y, int z,
+                                                    const NodeIn<LAT, NC, P>& in, P* __restrict__ gn,
+                                                    const P (&F)[NC][3], const P (&G)[NC][3],
+                                                    const double (&Fs)[3], P* fsum_out, bool nt) {
+    using L = Lat<LAT>;
+    const auto& gv = in.gv;
+    const auto& fprev = in.fprev;
     constexpr int D = L::D, Q = L::Q;
     using T = P;  // collision precision
     const size_t N = dm.N;
@@ -261,20 +309,8 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
         return pop_off<NC, P>(m);   // byte offset of node m's populations
     };
 
-    P gv[NC][Q];
-    if constexpr (NTLD) {
-        const unsigned off = pop_off<NC, P>(n);
-#pragma unroll
-        for (int a = 0; a < Q; ++a)
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                gv[c][a] = __builtin_nontemporal_load(reinterpret_cast<const P*>(
-                    reinterpret_cast<const char*>(pop_base<NC, Q>(g, c, a, N)) + off));
-    } else {
-        load_pops<L, NC, P>(g, n, N, gv);
-    }
     double rho[NC], mov[NC];
-    densities<L, NC, P>(gv, rref, n, N, rho, mov);
+    densities_ref<L, NC, P>(gv, in.ref, rho, mov);
     double rtot = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -289,7 +325,7 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
     double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : (double)ld(fsum_in, ((unsigned)n * D + k) * (unsigned)sizeof(P));
+        const double fk = kp.force_level ? Fs[k] : (double)fprev[k];
         u[k] = (j[k] + 0.5 * fk) / rtot;
     }
     // Push: direction a goes to n + e_a.  With the interleaved layout (N_c <= 2)
@@ -344,6 +380,21 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) st(fsum_out, ((unsigned)n * D + k) * (unsigned)sizeof(P), (P)Fs[k]);
+}
+
+// Steps 8-9 at node n, loading its inputs first.  The force sum of the previous
+// step is loaded whichever time level u takes: loaded inside that choice, it
+// was issued only after the populations had arrived (one more memory latency
+// per node).
+template <int LAT, int NC, typename P, bool MRT, bool NTLD = false>
+__device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, int n, int x, int y, int z,
+                                             const P* __restrict__ g, P* __restrict__ gn,
+                                             const float* __restrict__ rref, const P (&F)[NC][3],
+                                             const P (&G)[NC][3], const double (&Fs)[3], const P* fsum_in,
+                                             P* fsum_out, bool nt) {
+    NodeIn<LAT, NC, P> in;
+    load_node_inputs<LAT, NC, P, NTLD>(g, fsum_in, rref, n, dm.N, in);
+    collide_push_loaded<LAT, NC, P, MRT>(kp, dm, n, x, y, z, in, gn, F, G, Fs, fsum_out, nt);
 }
 
 // Steps 6-9 at node n reading the FP64 fields straight from global memory.
@@ -415,8 +466,15 @@ constexpr int kRlPts = kRlW * kRlH;
 constexpr int kPhiPer = (kPhiPts + 255) / 256;   // fill points per thread
 constexpr int kRlPer = (kRlPts + 255) / 256;
 
+// Waves per SIMD the z-marching kernel is compiled for: two (at most 256
+// registers per lane) for FP32 populations with one or two components, where
+// the MRT collision would otherwise take a few more and halve the occupancy;
+// the compiler's choice otherwise.
+template <int NC, typename P>
+constexpr int kZmarchWaves = (sizeof(P) == 4 && NC <= 2) ? 2 : 1;
+
 template <int NC, typename P, bool MRT, int DIR>
-__global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __restrict__ g,
+__global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(KParams kp, const P* __restrict__ g,
                                                         P* __restrict__ gn,
                                                         const float* __restrict__ rref,
                                                         const double* __restrict__ rt,
@@ -493,6 +551,15 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
     double rl_b1[2 * NC];
 #pragma unroll
     for (int f = 0; f < 2 * NC; ++f) rl_b1[f] = ld(rl_src(f) + zoff(start - DIR), col8);
+    // The node's inputs and its own column ahead (phi two planes, rt / ln f one
+    // plane along the march) are loaded one plane early, the first here: their
+    // latency overlaps the barrier and the ring stores instead of the stencil.
+    NodeIn<1, NC, P> in;
+    load_node_inputs<1, NC, P, true>(g, fsum_in, rref, col + start * plane, N, in);
+    double phi_a2 = ld(phig + zoff(start + 2 * DIR), col8);
+    double rl_a1[2 * NC];
+#pragma unroll
+    for (int f = 0; f < 2 * NC; ++f) rl_a1[f] = ld(rl_src(f) + zoff(start + DIR), col8);
     __syncthreads();
 
     const int cphi = (ty + 2) * kPhiW + tx + 2;  // this node in the phi tile
@@ -509,10 +576,9 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
         for (int f = 0; f < 2 * NC; ++f)
 #pragma unroll
             for (int k = 0; k < kRlPer; ++k) frl[f][k] = ld(rl_src(f) + a1off, rl_off[k]);
-        const double phi_a2 = ld(phi2, col8);
-        double rl_a1[2 * NC];
-#pragma unroll
-        for (int f = 0; f < 2 * NC; ++f) rl_a1[f] = ld(rl_src(f) + a1off, col8);
+        // keep these fill loads ahead of the node's work (the scheduler would
+        // otherwise sink them next to their use at the end of the iteration)
+        __builtin_amdgcn_sched_barrier(0);
 
         // plane start + (j - 1) DIR lives in phi slot j & 3, plane start + j DIR
         // in rt / ln f slot j & 1
@@ -535,8 +601,14 @@ __global__ __launch_bounds__(256) void k_collide_zmarch(KParams kp, const P* __r
         stencil_force<3, NC, P>(
             kp, phi_at, [&](int i, int dx, int dy, int dz) { return rl_at(i, dx, dy, dz); },
             [&](int i, int dx, int dy, int dz) { return rl_at(NC + i, dx, dy, dz); }, F, G, Fs);
-        collide_push<1, NC, P, MRT, true>(kp, dm, col + zz * plane, x, y, zz, g, gn, rref, F, G, Fs, fsum_in,
-                                          fsum_out, nt != 0);
+        collide_push_loaded<1, NC, P, MRT>(kp, dm, col + zz * plane, x, y, zz, in, gn, F, G, Fs, fsum_out,
+                                           nt != 0);
+        if (it + 1 < z1 - z0) {  // the next plane's inputs
+            load_node_inputs<1, NC, P, true>(g, fsum_in, rref, col + (zz + DIR) * plane, N, in);
+            phi_a2 = ld(phig + zoff(zz + 3 * DIR), col8);
+#pragma unroll
+            for (int f = 0; f < 2 * NC; ++f) rl_a1[f] = ld(rl_src(f) + zoff(zz + 2 * DIR), col8);
+        }
 
         // shift the own-column registers, store the filled planes, publish
         phi_b2 = phi_b1;

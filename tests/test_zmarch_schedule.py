@@ -1,13 +1,14 @@
 """CPU replay of the z-marching collide/stream kernel's data staging.
 
 The kernel (k_collide_zmarch) gives each 256-thread workgroup a 64 x 4 tile of
-(x, y) and a range of z planes, marched upward or downward, keeps phi in a 4-slot LDS ring (tile + halo 2),
-rt and ln f in a 2-slot ring (tile + halo 1), and the node's own column at
-z +- 1, z +- 2 in registers or fresh loads.  This replays that schedule with
-the kernel's index arithmetic (fill offsets, slot numbers, register shifts,
-block order over the XCDs) and checks, for every node of every plane, that
-each value the stencil reads is the field at the periodic neighbour the
-stencil means, and that every LDS and global index stays inside its buffer.
+(x, y) and a range of z planes, marched upward or downward, keeps phi in a
+4-slot LDS ring (tile + halo 2), rt and ln f in a 2-slot ring (tile + halo 1),
+and the node's own column at z +- 1, z +- 2 in registers (the values ahead
+loaded one plane early, with the node's populations).  This replays that
+schedule with the kernel's index arithmetic (fill offsets, slot numbers,
+register shifts, block order over the XCDs) and checks, for every node of every
+plane, that each value the stencil reads is the field at the periodic neighbour
+the stencil means, and that every LDS and global index stays inside its buffer.
 """
 import numpy as np
 import pytest
@@ -90,14 +91,15 @@ def replay(nx, ny, nz, zlen, remap=True, direction=1):
         phi_b2 = flat_phi[zoff(start - 2 * D) + col]
         phi_b1 = flat_phi[zoff(start - D) + col]
         rl_b1 = flat_rl[zoff(start - D) + col]
+        # the own column ahead is loaded one plane early (the first before the loop)
+        phi_a2 = flat_phi[zoff(start + 2 * D) + col]
+        rl_a1 = flat_rl[zoff(start + D) + col]
         cphi = (ty + 2) * PHI_W + tx + 2
         crl = (ty + 1) * RL_W + tx + 1
         for it in range(z1 - z0):
             zz = start + it * D
             fphi = [np.where(o >= 0, flat_phi[zoff(zz + 2 * D) + np.maximum(o, 0)], 0.0) for o in phi_off]
             frl = [np.where(o >= 0, flat_rl[zoff(zz + D) + np.maximum(o, 0)], 0.0) for o in rl_off]
-            phi_a2 = flat_phi[zoff(zz + 2 * D) + col]
-            rl_a1 = flat_rl[zoff(zz + D) + col]
             s0, r0 = (it + 1) & 3, it & 1
             for dx, dy, dz in PHI_OFFS:
                 d = dz * D
@@ -126,6 +128,11 @@ def replay(nx, ny, nz, zlen, remap=True, direction=1):
             n = col + zz * plane
             assert n.min() >= 0 and n.max() < plane * nz
             visits[zz, y, x] += 1
+            if it + 1 < z1 - z0:  # the next plane's node inputs and own column
+                nn = col + (zz + D) * plane
+                assert z0 <= zz + D < z1 and nn.min() >= 0 and nn.max() < plane * nz
+                phi_a2 = flat_phi[zoff(zz + 3 * D) + col]
+                rl_a1 = flat_rl[zoff(zz + 2 * D) + col]
             phi_b2, phi_b1 = phi_b1, s_phi[s0, cphi]
             rl_b1 = s_rl[r0, crl]
             for k in range(PHI_PER):
