@@ -121,7 +121,7 @@ def cpu_baseline(w, budget_s=15.0):
 
 
 def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, plain_subset=16,
-                  tol=1e-10, check_every=1000, accuracy_subset=8):
+                  tol=1e-10, check_every=1000, accuracy_subset=8, policy="largest_first"):
     """Batched VLE serving: FP32-population server vs the plain FP64 path.
 
     Requests: binary D2Q9 L x 8 slabs, L log-uniform in [64, 2048], feed z1
@@ -136,14 +136,14 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, pl
     p32 = F.Params.from_workload(w, precision="fp32")
     reqs, rejected = wl.serving_requests(n=n_requests, seed=0)
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
-    closed = serving.serve(srv, reqs, np.zeros(len(reqs)), tol, check_every, max_steps, tick_ms)
+    closed = serving.serve(srv, reqs, np.zeros(len(reqs)), tol, check_every, max_steps, tick_ms, policy=policy)
     srv.close()
     print(f"[bench] serving closed loop: {closed['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     rate = 0.8 * closed["solves_per_s"]
     arrivals = serving.poisson_arrivals(len(reqs), rate, seed=0)
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
     batched = {}
-    opened = serving.serve(srv, reqs, arrivals, tol, check_every, max_steps, tick_ms,
+    opened = serving.serve(srv, reqs, arrivals, tol, check_every, max_steps, tick_ms, policy=policy,
                            on_result=lambda rec, rho: batched.__setitem__(rec["i"], (rho, rec["steps"], rec["status"])))
     srv.close()
     print(f"[bench] serving open loop: {opened['solves_per_s']:.1f} solves/s, "
@@ -178,6 +178,7 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, pl
     return {
         "requests": len(reqs), "rejected_feed_draws": rejected, "tol": tol, "check_every": check_every,
         "max_steps": max_steps, "pool_MB": pool_mb, "tick_ms": tick_ms, "precision": "fp32 populations",
+        "admission": policy,
         "closed_loop": strip(closed),
         "open_loop": dict(strip(opened), arrival_rate_per_s=round(rate, 3)),
         "plain_fp64": {"subset": len(idx), "solves_per_s": round(plain_rate, 3),
@@ -201,6 +202,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched serving leg")
+    ap.add_argument("--serve-policy", default="largest_first", choices=["largest_first", "fifo"],
+                    help="order in which arrived requests are admitted")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-max-steps", type=int, default=50000)
     ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
@@ -316,7 +319,8 @@ def main():
         "mass_total": [float(m) for m in mass],
     }
     if not args.no_serving:
-        out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps)
+        out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps,
+                                       policy=args.serve_policy)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -9,6 +9,7 @@ another with the single-lattice solver.
 """
 from __future__ import annotations
 
+import heapq
 import time
 from collections import deque
 
@@ -37,28 +38,42 @@ def percentile(v, q):
 
 
 def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms=20.0,
-          time_limit_s=None, on_result=None):
+          time_limit_s=None, on_result=None, policy="largest_first"):
     """Run the request stream through the server.  Wall-clock times in seconds
-    from the start; arrivals[i] is request i's arrival time."""
-    order = np.argsort(arrivals)
+    from the start; arrivals[i] is request i's arrival time.  policy is the
+    order in which arrived, not yet admitted requests are offered to the
+    server: "largest_first" (the longest lattices first: each runs on one
+    workgroup, so the last long solve to start sets the makespan) or "fifo"."""
+    if policy not in ("largest_first", "fifo"):
+        raise ValueError(f"unknown admission policy {policy!r}")
+    order = np.argsort(arrivals, kind="stable")
     pending = deque(int(i) for i in order)
+    waiting = []  # heap of arrived requests: (priority, arrival rank, index)
+    rank = 0
     inflight = {}
     done = []
     t0 = time.perf_counter()
     ticks = 0
     rejected_admissions = 0
-    while pending or inflight:
+    while pending or waiting or inflight:
         now = time.perf_counter() - t0
         while pending and arrivals[pending[0]] <= now:
-            i = pending[0]
+            i = pending.popleft()
+            prio = -reqs[i]["L"] * reqs[i]["ny"] if policy == "largest_first" else 0
+            heapq.heappush(waiting, (prio, rank, i))
+            rank += 1
+        while waiting:
+            i = waiting[0][2]
             r = reqs[i]
             rid = server.submit(request_field(r), (r["L"], r["ny"]), tol, check_every, max_steps)
             if rid is None:
                 rejected_admissions += 1
                 break
-            pending.popleft()
+            heapq.heappop(waiting)
             inflight[rid] = i
         if not inflight:
+            if waiting:
+                raise RuntimeError("a request cannot be admitted into an empty server")
             if pending:
                 wait = arrivals[pending[0]] - (time.perf_counter() - t0)
                 if wait > 0:
