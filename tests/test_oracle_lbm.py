@@ -295,6 +295,75 @@ def test_mrt_with_single_rate_is_bgk(name):
         assert np.max(np.abs(a.g - b.g)) < 1e-11
 
 
+def _group_projectors(name):
+    """Orthogonal projectors onto the moment groups, built here from the
+    lattice velocities alone: density {1}; momentum {e_k}; energy {|e|^2}
+    made orthogonal to {1}; traceless stress {e_x^2 - e_y^2, e_y^2 - e_z^2,
+    e_x e_y, e_y e_z, e_x e_z} (D2Q9: the first and e_x e_y); ghost = the
+    orthogonal complement of the four (plain inner product over directions)."""
+    e, _ = lat.lattice(name)
+    e = e.astype(float)
+    Q, D = e.shape
+    x, y = e[:, 0], e[:, 1]
+    z = e[:, 2] if D == 3 else np.zeros(Q)
+    e2 = (e ** 2).sum(axis=1)
+    spans = {"rho": [np.ones(Q)], "j": [e[:, k] for k in range(D)],
+             "e": [e2 - e2.mean()],
+             "nu": ([x * x - y * y, x * y] if D == 2 else
+                    [x * x - y * y, y * y - z * z, x * y, y * z, x * z])}
+    P = {}
+    for g, vecs in spans.items():
+        q, _ = np.linalg.qr(np.array(vecs).T)
+        P[g] = q @ q.T
+    P["ghost"] = np.eye(Q) - sum(P.values())
+    return P
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_mrt_relaxes_each_moment_group_at_its_rate(name):
+    """MRT away from S = I/tau, on a uniform state (no gradients: no force,
+    streaming is the identity), so one step is one collision.  S = 1 on every
+    group sends all moments to equilibrium, which gives g_eq of the same
+    conserved moments; then, with distinct rates per group, the part of
+    g* - g_eq in each group subspace must be (1 - s_group) times that of
+    g - g_eq, and the density group must not move.  A row of the basis in the
+    wrong group, a wrong rate or a sign slip in the relaxation fails this."""
+    rng = np.random.default_rng(11)
+    w = wl.WORKLOADS["binary_slab_2d"]
+    mix = mixture_of(w)
+    shape = (3, 2) if name == "D2Q9" else (2, 2, 2)
+    N = int(np.prod(shape))
+    _, groups = lat.mrt_basis(name)
+    rates = {"rho": 0.77, "j": 1.31, "nu": 0.64, "e": 1.52, "ghost": 1.13}
+    S = np.array([rates[g] for g in groups])
+    P = _group_projectors(name)
+    rL, _, _ = w.phase_densities()
+    rL_arr = np.asarray(rL, float)
+    rho = np.repeat(rL_arr[:, None], N, axis=1)
+    base = lbm.OracleLBM(mix, name, shape, tau=1.0, collision="MRT", mrt_S=np.ones(len(S)))
+    base.init(rho)
+    Q = base.Q
+    # one node's populations (every node the same): the equilibrium at rest plus
+    # a random deviation in every direction
+    g0 = base.g[:, :, :1] + 0.01 * rL_arr[:, None, None] * rng.uniform(-1, 1, (2, Q, 1))
+    g0 = np.repeat(g0, N, axis=2)
+    runs = {}
+    for key, Srun in (("eq", np.ones(len(S))), ("S", S)):
+        o = lbm.OracleLBM(mix, name, shape, tau=1.0, collision="MRT", mrt_S=Srun)
+        o.g[:] = g0
+        o.run(1)
+        assert np.max(np.abs(o.g - o.g[:, :, :1])) < 1e-15  # still uniform
+        runs[key] = o.g[:, :, 0].copy()
+    geq, gs, g = runs["eq"], runs["S"], g0[:, :, 0]
+    for c in range(2):
+        assert np.allclose(P["rho"] @ (gs[c] - g[c]), 0.0, atol=1e-14)
+        for grp in ("j", "nu", "e", "ghost"):
+            lhs = P[grp] @ (gs[c] - geq[c])
+            rhs = (1.0 - rates[grp]) * (P[grp] @ (g[c] - geq[c]))
+            assert np.max(np.abs(P[grp] @ (g[c] - geq[c]))) > 1e-6 or grp == "j", grp
+            np.testing.assert_allclose(lhs, rhs, atol=1e-13, err_msg=f"{name} component {c} group {grp}")
+
+
 # ------------------------------------------------------- fixed point / physics
 def test_converges_to_discrete_equilibrium():
     """After convergence the LBM state is the discrete equilibrium mu_i = const
