@@ -364,6 +364,55 @@ def test_mrt_relaxes_each_moment_group_at_its_rate(name):
             np.testing.assert_allclose(lhs, rhs, atol=1e-13, err_msg=f"{name} component {c} group {grp}")
 
 
+def test_mrt_forcing_enters_each_group_with_its_factor():
+    """MRT away from S = I/tau with a force: on a two-phase slab with random
+    populations, one oracle step is undone streaming-wise (each direction
+    shifted back by -e_a), and at every node the part of g* - g_eq in each
+    group subspace must be (1 - s) times that of g - g_eq plus (1 - s/2) times
+    that of the forcing vector F_a, with g_eq and F_a from the single-node
+    equilibrium and forcing (pinned by their closed-form moments), u and F_i
+    from the state's fields and grad rho_i by central differences (eq1stder).
+    With s = 1/tau in every group this is eq. eqLBEMCa."""
+    rng = np.random.default_rng(5)
+    name, nx, ny = "D2Q9", 16, 3
+    w = wl.WORKLOADS["binary_slab_2d"]
+    mix = mixture_of(w)
+    e, _ = lat.lattice(name)
+    _, groups = lat.mrt_basis(name)
+    rates = {"rho": 0.8, "j": 1.35, "nu": 0.7, "e": 1.45, "ghost": 1.2}
+    S = np.array([rates[g] for g in groups])
+    P = _group_projectors(name)
+    rho = np.repeat(slab(nx, w)[:, None, :], ny, axis=1).reshape(2, -1)
+    o = lbm.OracleLBM(mix, name, (nx, ny), tau=1.0, collision="MRT", mrt_S=S)
+    o.init(rho)
+    o.g += 2e-3 * o.g[:, :1, :] * rng.uniform(-1, 1, o.g.shape)
+    f = o.fields()
+    g = o.g.copy().reshape(2, 9, ny, nx)
+    o.run(1)
+    post = o.g.reshape(2, 9, ny, nx)
+    gs = np.stack([np.stack([np.roll(post[c, a], (-e[a, 1], -e[a, 0]), axis=(0, 1)) for a in range(9)])
+                   for c in range(2)])
+    rho_mass = (f["rho_molar"] * np.asarray(mix.M)[:, None]).reshape(2, ny, nx)
+    grad = np.stack([(np.roll(rho_mass, -1, axis=2) - np.roll(rho_mass, 1, axis=2)) / 2.0,
+                     (np.roll(rho_mass, -1, axis=1) - np.roll(rho_mass, 1, axis=1)) / 2.0], axis=1)
+    force = f["force"].reshape(2, 2, ny, nx)
+    u = f["u"].reshape(2, ny, nx)
+    assert np.max(np.abs(force)) > 1e-4   # the interfaces exert a force
+    worst = 0.0
+    for yy in range(ny):
+        for xx in range(nx):
+            for c in range(2):
+                uu = u[:, yy, xx]
+                geq = o.equilibrium(rho_mass[c, yy, xx], uu)
+                Fa = o.forcing(force[c, :, yy, xx], grad[c, :, yy, xx], uu)
+                for grp in ("rho", "j", "nu", "e", "ghost"):
+                    lhs = P[grp] @ (gs[c, :, yy, xx] - geq)
+                    rhs = ((1.0 - rates[grp]) * (P[grp] @ (g[c, :, yy, xx] - geq))
+                           + (1.0 - rates[grp] / 2.0) * (P[grp] @ Fa))
+                    worst = max(worst, float(np.max(np.abs(lhs - rhs))))
+    assert worst < 1e-13, worst
+
+
 # ------------------------------------------------------- fixed point / physics
 def test_converges_to_discrete_equilibrium():
     """After convergence the LBM state is the discrete equilibrium mu_i = const
