@@ -120,7 +120,7 @@ def cpu_baseline(w, budget_s=15.0):
                       f"FP64, {w.collision}, {dt:.1f} s"}
 
 
-def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=20.0, plain_subset=16,
+def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, plain_subset=16,
                   tol=1e-10, check_every=1000, accuracy_subset=8, policy="largest_first"):
     """Batched VLE serving: FP32-population server vs the plain FP64 path.
 
@@ -206,6 +206,8 @@ def main():
                     help="order in which arrived requests are admitted")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-max-steps", type=int, default=50000)
+    ap.add_argument("--serve-tick-ms", type=float, default=50.0,
+                    help="wall-clock budget of one batched-kernel tick")
     ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
                     help="uniform: the workload's mean composition everywhere (a steady state; the "
                          "per-step work does not depend on the state)")
@@ -320,6 +322,7 @@ def main():
     }
     if not args.no_serving:
         out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps,
+                                       tick_ms=args.serve_tick_ms,
                                        policy=args.serve_policy)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
