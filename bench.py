@@ -206,6 +206,7 @@ def main():
                     help="order in which arrived requests are admitted")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-max-steps", type=int, default=50000)
+    ap.add_argument("--serve-pool-mb", type=int, default=256, help="HBM budget of the server pool")
     ap.add_argument("--serve-tick-ms", type=float, default=50.0,
                     help="wall-clock budget of one batched-kernel tick")
     ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
@@ -322,7 +323,7 @@ def main():
     }
     if not args.no_serving:
         out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps,
-                                       tick_ms=args.serve_tick_ms,
+                                       tick_ms=args.serve_tick_ms, pool_mb=args.serve_pool_mb,
                                        policy=args.serve_policy)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
