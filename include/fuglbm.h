@@ -222,12 +222,13 @@ int fl_server_request_bytes(const fl_server* srv, int nx, int ny, int nz, size_t
 int fl_server_submit(fl_server* srv, int nx, int ny, int nz, const double* rho_molar, double tol,
                      long check_every, long max_steps, uint64_t* id);
 
-/* One tick (synchronous): every running request advances by up to `steps`
- * steps, and stops early once max_ms milliseconds of device time have passed
- * since its workgroup started (checked every 8 steps, so a request may run up
- * to 8 steps past the limit; max_ms <= 0: no time limit), so that large and
- * small requests leave the tick together.  *active receives the requests still
- * running. */
+/* One tick (synchronous): the running requests, oldest first and at most as
+ * many as the device holds server workgroups at once (the rest wait, admitted,
+ * for a later tick), advance by up to `steps` steps each, and stop early once
+ * max_ms milliseconds of device time have passed since their workgroup
+ * started (checked every 8 steps, so a request may run up to 8 steps past the
+ * limit; max_ms <= 0: no time limit), so that large and small requests leave
+ * the tick together.  *active receives the requests still running. */
 int fl_server_tick(fl_server* srv, long steps, double max_ms, int* active);
 
 /* Ids of finished, not yet collected requests (up to cap); *n the count. */

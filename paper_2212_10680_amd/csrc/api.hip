@@ -233,6 +233,8 @@ int setup(fl_solver* s, const fl_params* p) {
             s->lc.block_k2 = v;
         if ((q = std::strstr(t, "remap=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.xcd_remap = v != 0;
         if ((q = std::strstr(t, "nt=")) && std::sscanf(q + 3, "%d", &v) == 1) s->lc.nt_store = v != 0;
+        if ((q = std::strstr(t, "serve_cap=")) && std::sscanf(q + 10, "%d", &v) == 1 && v >= -1)
+            s->lc.serve_cap = v;
         if ((q = std::strstr(t, "serve=")) && std::sscanf(q + 6, "%d", &v) == 1 && (v == 256 || v == 512 || v == 1024))
             s->lc.serve_block = v;
         if ((q = std::strstr(t, "fused=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.fused = v != 0;
@@ -911,7 +913,16 @@ int fl_server_tick(fl_server* s, long steps, double max_ms, int* active) {
         if (budget < 1) budget = 1;
     }
     std::vector<int> run;
-    for (int k = 0; k < (int)s->reqs.size(); ++k)
+    // Advance at most as many requests as the device holds workgroups at once,
+    // oldest first: a workgroup beyond that would only start when another
+    // leaves at the end of its time slice, and take the rest of the slice.
+    if (s->cfg.lc.serve_cap < 0) {
+        int blocks = 0;
+        SRV_TRY(s, fl::serve_resident_blocks(s->cfg.lc, &blocks));
+        s->cfg.lc.serve_cap = blocks > 0 ? blocks : 0;
+    }
+    const int cap = s->cfg.lc.serve_cap;
+    for (int k = 0; k < (int)s->reqs.size() && (cap <= 0 || (int)run.size() < cap); ++k)
         if (s->reqs[k].d.status == fl::kSlotRunning) run.push_back(k);
     const int n = (int)run.size();
     if (n > 0 && steps > 0) {

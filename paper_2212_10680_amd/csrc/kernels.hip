@@ -1232,6 +1232,30 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
     }
 }
 
+hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks) {
+    *blocks = 0;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        auto go = [&](auto bsc) {
+            constexpr int BS = decltype(bsc)::value;
+            e = lc.mrt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve_tick<LAT, NC, P, true, BS>, BS, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve_tick<LAT, NC, P, false, BS>, BS, 0);
+        };
+        if (lc.serve_block >= 1024)
+            go(std::integral_constant<int, 1024>{});
+        else if (lc.serve_block >= 512)
+            go(std::integral_constant<int, 512>{});
+        else
+            go(std::integral_constant<int, 256>{});
+    });
+    if (e == hipSuccess) *blocks = cus * (per_cu > 0 ? per_cu : 1);
+    return e;
+}
+
 hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs, int nslots,
                              long long steps, long long clock_budget) {
     if (nslots <= 0) return hipSuccess;

@@ -18,6 +18,8 @@ struct LaunchCfg {
     bool xcd_remap = true;  // XCD-contiguous block order
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
+    int serve_cap = -1;     // most requests advanced per tick, oldest first
+                            // (-1: as many as the device holds at once, 0: all running)
     bool fused = false;     // one-launch step (FUGLBM_TUNE fused=1) when the lattice allows it
     bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (set per solver)
     bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
@@ -81,6 +83,8 @@ enum { kSlotRunning = 0, kSlotConverged = 1, kSlotMaxSteps = 2, kSlotNumeric = 3
 // Advance every slot of descs[0..nslots) by up to `steps` steps, one workgroup
 // per slot, each stopping early once clock_budget ticks of the device wall
 // clock have passed (<= 0: no limit); descs is updated in place.
+// Workgroups of the batched-server kernel that the device holds at once.
+hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks);
 hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs,
                              int nslots, long long steps, long long clock_budget);
 

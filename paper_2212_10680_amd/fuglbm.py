@@ -345,8 +345,10 @@ class Server:
         return rid.value
 
     def tick(self, steps, max_ms=0.0):
-        """Advance every running request by up to `steps` steps or max_ms of
-        device time (<= 0: no limit); returns the number still running."""
+        """Advance the running requests (oldest first, at most as many as the
+        device holds server workgroups at once) by up to `steps` steps or
+        max_ms of device time (<= 0: no limit); returns the number still
+        running."""
         a = C.c_int(0)
         self._check(self.lib.fl_server_tick(self.h, int(steps), float(max_ms), C.byref(a)), "fl_server_tick")
         return a.value

@@ -166,3 +166,29 @@ def test_convergence_status():
     rho, steps, res, status = out[0]
     print(f"  steps {steps} residual {res:.2e}", flush=True)
     assert status == F.FL_OK and res < 1e-8 and steps % 500 == 0
+
+
+def test_request_cap_per_tick_bitwise():
+    """Advancing at most two requests per tick (oldest first; the rest wait
+    admitted) gives every request the same result, bit for bit, as advancing
+    all of them, and every request completes."""
+    import os
+
+    announce("request cap per tick")
+    reqs = some_requests(5, seed=7)
+    old = os.environ.get("FUGLBM_TUNE")
+    try:
+        os.environ["FUGLBM_TUNE"] = "serve_cap=2"
+        capped = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300)
+        os.environ["FUGLBM_TUNE"] = "serve_cap=0"
+        free = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300)
+    finally:
+        if old is None:
+            os.environ.pop("FUGLBM_TUNE", None)
+        else:
+            os.environ["FUGLBM_TUNE"] = old
+    assert sorted(capped) == sorted(free) == list(range(len(reqs)))
+    for i in range(len(reqs)):
+        a, b = capped[i], free[i]
+        assert a[1] == b[1] and a[2] == b[2] and a[3] == b[3], i
+        assert np.array_equal(a[0], b[0]), i
