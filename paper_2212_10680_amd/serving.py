@@ -51,6 +51,7 @@ def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms
     waiting = []  # heap of arrived requests: (priority, arrival rank, index)
     rank = 0
     inflight = {}
+    admitted = {}
     done = []
     t0 = time.perf_counter()
     ticks = 0
@@ -71,6 +72,7 @@ def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms
                 break
             heapq.heappop(waiting)
             inflight[rid] = i
+            admitted[i] = time.perf_counter() - t0
         if not inflight:
             if waiting:
                 raise RuntimeError("a request cannot be admitted into an empty server")
@@ -87,7 +89,8 @@ def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms
             rho, steps, res, status = server.result(rid, r["L"] * r["ny"])
             t = time.perf_counter() - t0
             rec = {"i": i, "L": r["L"], "steps": steps, "residual": res, "status": status,
-                   "arrival": float(arrivals[i]), "done": t, "latency": t - float(arrivals[i])}
+                   "arrival": float(arrivals[i]), "admitted": admitted[i], "done": t,
+                   "latency": t - float(arrivals[i])}
             done.append(rec)
             if on_result:
                 on_result(rec, rho)
