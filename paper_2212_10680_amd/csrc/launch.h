@@ -80,11 +80,11 @@ struct SlotDesc {
 };
 enum { kSlotRunning = 0, kSlotConverged = 1, kSlotMaxSteps = 2, kSlotNumeric = 3 };
 
+// Workgroups of the batched-server kernel that the device holds at once.
+hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks);
 // Advance every slot of descs[0..nslots) by up to `steps` steps, one workgroup
 // per slot, each stopping early once clock_budget ticks of the device wall
 // clock have passed (<= 0: no limit); descs is updated in place.
-// Workgroups of the batched-server kernel that the device holds at once.
-hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks);
 hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs,
                              int nslots, long long steps, long long clock_budget);
 
