@@ -454,9 +454,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
 //   rt, ln f   plane z (tile + halo 1) in a ring of 2 slots, while plane z+1 is
 //              loaded into the other;
 // the node's own column supplies phi(z-2) and rt, ln f(z-1) from registers
-// (values of earlier planes) and phi(z+2), rt, ln f(z+1) from the lines the
-// fill of those planes is bringing into the caches.  The per-node arithmetic is
-// stencil_force + collide_push, as in k_collide_stream.
+// (values of earlier planes) and phi(z+2), rt, ln f(z+1) from registers loaded
+// one plane early, together with the node's populations.  The per-node
+// arithmetic is stencil_force + collide_push_loaded, as in k_collide_stream.
 constexpr int kZX = 64, kZY = 4;
 constexpr int kPhiW = kZX + 4, kPhiH = kZY + 4;  // phi tile + halo 2
 constexpr int kRlW = kZX + 2, kRlH = kZY + 2;    // rt / ln f tile + halo 1
