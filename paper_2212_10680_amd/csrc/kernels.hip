@@ -874,7 +874,7 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
                                  void* fsum_out) {
     const int bs = lc.block_k2;
     const int nb = (kp.N + bs - 1) / bs;
-    const int ch = xcd_chunk_for(lc, nb);
+    const int ch = lc.xcd_remap_k2 ? xcd_chunk_for(lc, nb) : 0;
     const int nt = lc.nt_store ? 1 : 0;
     const int rev = lc.reverse_k2 ? 1 : 0;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {

@@ -16,6 +16,7 @@ struct LaunchCfg {
     int block_k1 = 128;     // threads per block of the moments/EOS kernel
     int block_k2 = 128;     // threads per block of the collide/stream kernel
     bool xcd_remap = true;  // XCD-contiguous block order
+    bool xcd_remap_k2 = true;  // the same for the plain collide/stream kernel
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
     int serve_cap = -1;     // most requests advanced per tick, oldest first
