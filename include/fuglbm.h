@@ -156,6 +156,14 @@ int fl_step(fl_solver* s, long nsteps);
 int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names,
                   int* nkernels);
 
+/* Same as fl_step_timed, but with the events only around the kernels of
+ * every `every`-th step (steps 0, every, 2 every, ... of this call), so that
+ * a long timed run carries a small fraction of the event overhead.
+ * kernel_ms[k] is summed over the timed steps; *timed_steps (optional)
+ * receives their number.  FL_EINVAL for every < 1. */
+int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms, const char** names,
+                        int* nkernels, long* timed_steps);
+
 /* Number of steps done since fl_set_state. */
 long fl_steps_done(const fl_solver* s);
 

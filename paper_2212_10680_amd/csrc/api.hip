@@ -52,6 +52,7 @@ struct fl_solver {
     double* h_red = nullptr;
     long steps = 0;
     bool snap_valid = false;
+    std::vector<hipEvent_t> timing_events;  // fl_step_timed's, created on its first call
     std::string last_error;
 };
 
@@ -466,6 +467,8 @@ int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_
 void fl_destroy(fl_solver* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->timing_events)
+        if (e) (void)hipEventDestroy(e);
     if (s->own_mem && s->mem) (void)hipFree(s->mem);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->h_err) (void)hipHostFree(s->h_err);
@@ -532,32 +535,54 @@ int fl_step(fl_solver* s, long nsteps) {
     return check_err(s);
 }
 
-int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names, int* nkernels) {
-    if (!s || nsteps < 0 || !kernel_ms || !nkernels || *nkernels < 2) return FL_EINVAL;
+int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms, const char** names,
+                        int* nkernels, long* timed_steps) {
+    if (!s || nsteps < 0 || every < 1 || !kernel_ms || !nkernels || *nkernels < 2) return FL_EINVAL;
     static const char* kNames[2] = {"k_moments_eos", "k_collide_stream"};
     static const char* kFused[1] = {"k_fused_step"};
     const bool fused = s->fused;
     const long chunk = 256;
-    std::vector<hipEvent_t> ev(3 * chunk);
-    for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
+    // events are created once per solver (creating 768 of them takes
+    // milliseconds, which a timed run should not include)
+    if (s->timing_events.empty()) {
+        std::vector<hipEvent_t> made(3 * chunk, nullptr);
+        for (auto& e : made) {
+            const hipError_t c = hipEventCreate(&e);
+            if (c != hipSuccess) {
+                for (hipEvent_t x : made)
+                    if (x) (void)hipEventDestroy(x);
+                return hip_fail(s, c, "hipEventCreate");
+            }
+        }
+        s->timing_events.swap(made);
+    }
+    std::vector<hipEvent_t>& ev = s->timing_events;
     double acc[2] = {0.0, 0.0};
+    long timed = 0;
     int rc = FL_OK;
-    for (long done = 0; done < nsteps && rc == FL_OK; done += chunk) {
-        const long m = std::min(chunk, nsteps - done);
-        for (long k = 0; k < m && rc == FL_OK; ++k) rc = one_step(s, &ev[3 * k]);
+    // steps in chunks of `chunk` timed ones (the event pool), then one sync
+    for (long done = 0; done < nsteps && rc == FL_OK;) {
+        long j = 0;
+        for (; done < nsteps && j < chunk && rc == FL_OK; ++done) {
+            if (done % every == 0)
+                rc = one_step(s, &ev[3 * j++]);
+            else
+                rc = one_step(s, nullptr);
+        }
         if (rc != FL_OK) break;
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) { rc = hip_fail(s, e, "hipStreamSynchronize"); break; }
-        for (long k = 0; k < m; ++k) {
+        for (long k = 0; k < j; ++k) {
             float a = 0.f, b = 0.f;
             (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
             if (!fused) (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
             acc[0] += a;
             acc[1] += b;
         }
+        timed += j;
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != FL_OK) return rc;
+    if (timed_steps) *timed_steps = timed;
     if (fused) {
         kernel_ms[0] = acc[0];
         if (names) names[0] = kFused[0];
@@ -569,6 +594,10 @@ int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** nam
         *nkernels = 2;
     }
     return check_err(s);
+}
+
+int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names, int* nkernels) {
+    return fl_step_timed_every(s, nsteps, 1, kernel_ms, names, nkernels, nullptr);
 }
 
 long fl_steps_done(const fl_solver* s) { return s ? s->steps : -1; }

@@ -63,6 +63,8 @@ SIGNATURES = {
     "fl_set_state": (C.c_int, [_VP, _DP, _DP]),
     "fl_step": (C.c_int, [_VP, C.c_long]),
     "fl_step_timed": (C.c_int, [_VP, C.c_long, _DP, C.POINTER(C.c_char_p), C.POINTER(C.c_int)]),
+    "fl_step_timed_every": (C.c_int, [_VP, C.c_long, C.c_long, _DP, C.POINTER(C.c_char_p), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_long)]),
     "fl_steps_done": (C.c_long, [_VP]),
     "fl_get_fields": (C.c_int, [_VP, _DP, _DP, _DP, _DP]),
     "fl_get_populations": (C.c_int, [_VP, _DP]),
@@ -238,6 +240,17 @@ class Solver:
 
     def step(self, n):
         return self._check(self.lib.fl_step(self.h, int(n)), "fl_step")
+
+    def step_timed_every(self, n, every):
+        """Advance n steps, timing the kernels of every `every`-th one; returns
+        ({kernel name: mean ms per launch over the timed steps}, timed steps)."""
+        ms = np.zeros(8)
+        names = (C.c_char_p * 8)()
+        k = C.c_int(8)
+        t = C.c_long(0)
+        self._check(self.lib.fl_step_timed_every(self.h, int(n), int(every), _dp(ms), names, C.byref(k),
+                                                 C.byref(t)), "fl_step_timed_every")
+        return {names[i].decode(): ms[i] / max(t.value, 1) for i in range(k.value)}, t.value
 
     def step_timed(self, n):
         ms = np.zeros(8)

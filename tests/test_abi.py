@@ -118,3 +118,10 @@ def test_lattice_table(lib, name):
 def test_status_strings(lib):
     for st in range(-7, 1):
         assert lib.fl_status_string(st)
+
+
+def test_sampled_timing_rejects_without_a_gpu_call(lib):
+    ms = (C.c_double * 8)()
+    k = C.c_int(8)
+    t = C.c_long(0)
+    assert lib.fl_step_timed_every(None, 10, 4, ms, None, C.byref(k), C.byref(t)) == F.FL_EINVAL
