@@ -295,3 +295,27 @@ def test_run_until_residual():
     conv, done, res = s.run_until(1e-8, 500, 40000)
     print(f"  converged={conv} steps={done} residual={res:.2e}", flush=True)
     assert conv and res < 1e-8 and done % 500 == 0
+
+
+def test_sampled_timing_steps_like_plain_steps():
+    """fl_step_timed_every advances exactly like fl_step (bitwise), times the
+    kernels of steps 0, every, 2 every, ... of the call, and rejects every < 1."""
+    w = wl.WORKLOADS["binary_slab_3d"].scaled((64, 8, 6))
+    announce("sampled timing")
+    rho, u = wl.initial_field(w)
+    a = F.Solver(F.Params.from_workload(w, precision="fp32"))
+    b = F.Solver(F.Params.from_workload(w, precision="fp32"))
+    a.set_state(rho, u)
+    b.set_state(rho, u)
+    kavg, timed = a.step_timed_every(10, 4)
+    b.step(10)
+    assert timed == 3 and a.steps == b.steps == 10
+    assert set(kavg) == {"k_moments_eos", "k_collide_zmarch"} and all(v > 0 for v in kavg.values())
+    kavg, timed = a.step_timed_every(600, 1)   # more timed steps than one event pool holds
+    b.step(600)
+    assert timed == 600
+    assert np.array_equal(a.populations(), b.populations())
+    with pytest.raises(F.FLError):
+        a.step_timed_every(1, 0)
+    a.close()
+    b.close()
