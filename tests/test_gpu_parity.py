@@ -12,7 +12,8 @@ import pytest
 from paper_2212_10680_amd import fuglbm as F
 from paper_2212_10680_amd import workloads as wl
 
-from _util import direction_map, oracle_for, rel, smooth_3d_field
+from _util import (bulk_values, direction_map, flash_errors_percent, mixture_of, oracle_for, rel,
+                   smooth_3d_field)
 
 pytestmark = pytest.mark.gpu
 
@@ -319,3 +320,40 @@ def test_sampled_timing_steps_like_plain_steps():
         a.step_timed_every(1, 0)
     a.close()
     b.close()
+
+
+def test_bench_config_full_run_vs_oracle_and_flash():
+    """The benchmark configuration at full size over its full run length (D3Q19
+    128^3 binary slab, FP32 populations + FP64 EOS, BGK tau 0.8, 20 000 steps,
+    default kernels): every (y, z) column identical, the column within 1e-4 of
+    the FP64 oracle run of the same problem on 128 x 2 x 2 (the slab is uniform
+    along y and z), and the bulk phase errors against the flash equal to the
+    oracle's within 1e-3 percentage points."""
+    w = wl.WORKLOADS["binary_slab_3d"]
+    nx = w.shape[0]
+    announce(f"bench configuration {w.shape}, 20000 steps")
+    rho, u = wl.initial_field(w)
+    s = F.Solver(F.Params.from_workload(w, precision="fp32"))
+    s.set_state(rho, u)
+    assert list(s.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch"]
+    s.step(19999)
+    f = s.fields()["rho_molar"].reshape(2, w.shape[2], w.shape[1], nx)
+    s.close()
+    assert np.array_equal(f, np.broadcast_to(f[:, :1, :1, :], f.shape))
+    ws = w.scaled((nx, 2, 2))
+    o = oracle_for(ws)
+    r2, u2 = wl.initial_field(ws)
+    o.init(r2.reshape(2, -1), None if u2 is None else u2.reshape(3, -1))
+    o.run(20000)
+    ref = o.fields()["rho_molar"].reshape(2, 2, 2, nx)[:, 0, 0, :]
+    col = f[:, 0, 0, :]
+    err = rel(col, ref)
+    mix = mixture_of(w)
+    z = ref.sum(axis=1) / ref.sum()
+    eg = flash_errors_percent(mix, z, *bulk_values(col))
+    eo = flash_errors_percent(mix, z, *bulk_values(ref))
+    print(f"  column vs oracle {err:.2e}; errors vs flash (%): GPU {eg}, oracle {eo}", flush=True)
+    assert err < 1e-4
+    for phase in eg:
+        for k in eg[phase]:
+            assert abs(eg[phase][k] - eo[phase][k]) < 1e-3, (phase, k)
