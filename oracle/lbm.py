@@ -50,6 +50,7 @@ class _Params(C.Structure):
         ("e", C.c_double * (MAXQ * 3)), ("w", C.c_double * MAXQ),
         ("Mm", C.c_double * (MAXQ * MAXQ)), ("Minv", C.c_double * (MAXQ * MAXQ)),
         ("S", C.c_double * MAXQ),
+        ("stencil", C.c_int),
     ]
 
 
@@ -102,10 +103,13 @@ class OracleLBM:
                 unless ``mrt_S`` is given)
     force_level : 0 = previous step's force in u (literal step 1), 1 = same step
     standard_force : use the standard-LBM force variant (eqForceGen)
+    stencil   : 'axis' (the paper's eq1stder / eq2ndder) or 'isotropic'
+                (lattice-weighted stencils; a reading for 3-D droplets, which
+                leave the EOS domain with the axis stencils)
     """
 
     def __init__(self, mixture: Mixture, lattice="D2Q9", shape=(64, 8), tau=1.0,
-                 collision="BGK", force_level=0, mrt_S=None, standard_force=False):
+                 collision="BGK", force_level=0, mrt_S=None, standard_force=False, stencil="axis"):
         self.mix = mixture
         self.lattice = lattice
         e, w = lat.lattice(lattice)
@@ -128,6 +132,9 @@ class OracleLBM:
         P.collision = 1 if collision == "MRT" else 0
         P.force_level = int(force_level)
         P.standard_force = int(bool(standard_force))
+        if stencil not in ("axis", "isotropic"):
+            raise ValueError(stencil)
+        P.stencil = 1 if stencil == "isotropic" else 0
         P.RT = mixture.RT
         P.tau = float(tau)
         P.cs2 = lat.CS2

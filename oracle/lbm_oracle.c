@@ -58,6 +58,8 @@ typedef struct {
     double Mm[ORC_MAXQ * ORC_MAXQ];    /* MRT basis (rows = moments) */
     double Minv[ORC_MAXQ * ORC_MAXQ];
     double S[ORC_MAXQ];
+    int stencil;           /* 0: the paper's axis stencils (eq1stder, eq2ndder);
+                              1: isotropic lattice stencils (reading for 3-D droplets) */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_EDOMAIN = -2, ORC_ENOMEM = -3 };
@@ -207,6 +209,28 @@ static void collide(const orc_params* P, const double* g, const double* geq, con
  * without collision).  Any output may be NULL.  rho_molar/lnf are [nc][N],
  * u [D][N], p [N], force [nc][D][N] (this step's F_i).  Returns the first
  * domain error or 0. */
+/* Isotropic lattice stencils (the weights and velocities of the lattice):
+ * grad f = (1/c_s^2) sum_a w_a e_a f(x + e_a), lap f = (2/c_s^2) sum_a w_a
+ * (f(x + e_a) - f(x)); on a field that varies along one axis they reduce to
+ * the central differences of eq1stder and eq2ndder. */
+static double iso_grad(const orc_params* P, const double* f, long x, long y, long z, int k) {
+    double s = 0.0;
+    for (int a = 1; a < P->Q; ++a) {
+        const double* e = &P->e[3 * a];
+        if (e[k] != 0.0) s += P->w[a] * e[k] * f[nidx(P, x + (long)e[0], y + (long)e[1], z + (long)e[2])];
+    }
+    return s / P->cs2;
+}
+
+static double iso_lap(const orc_params* P, const double* f, long n, long x, long y, long z) {
+    double s = 0.0;
+    for (int a = 1; a < P->Q; ++a) {
+        const double* e = &P->e[3 * a];
+        s += P->w[a] * (f[nidx(P, x + (long)e[0], y + (long)e[1], z + (long)e[2])] - f[n]);
+    }
+    return 2.0 * s / P->cs2;
+}
+
 static int fields_and_force(const orc_params* P, const double* g, const double* fprev,
                             double* rho_i, double* jm, double* u, double* rt_i, double* p,
                             double* lnf, double* mu_i, double* force, long* bad_node) {
@@ -259,9 +283,13 @@ static int fields_and_force(const orc_params* P, const double* g, const double* 
         for (int jc = 0; jc < nc; ++jc) {
             const double* r = rt_i + (long)jc * N;
             double L = 0.0;
-            for (int k = 0; k < D; ++k) {
-                const long dx = (k == 0), dy = (k == 1), dz = (k == 2);
-                L += r[nidx(P, x + dx, y + dy, z + dz)] - 2.0 * r[n] + r[nidx(P, x - dx, y - dy, z - dz)];
+            if (P->stencil == 1) {
+                L = iso_lap(P, r, n, x, y, z);
+            } else {
+                for (int k = 0; k < D; ++k) {
+                    const long dx = (k == 0), dy = (k == 1), dz = (k == 2);
+                    L += r[nidx(P, x + dx, y + dy, z + dz)] - 2.0 * r[n] + r[nidx(P, x - dx, y - dy, z - dz)];
+                }
             }
             lap[jc] = L;
         }
@@ -283,13 +311,14 @@ static int fields_and_force(const orc_params* P, const double* g, const double* 
                 for (int k = 0; k < D; ++k) {
                     const long dx = (k == 0), dy = (k == 1), dz = (k == 2);
                     const long np = nidx(P, x + dx, y + dy, z + dz), nm = nidx(P, x - dx, y - dy, z - dz);
-                    const double dlnf = (lf[np] - lf[nm]) / 2.0;
-                    const double dmu = (mu[np] - mu[nm]) / 2.0;
+                    const int iso = P->stencil == 1;
+                    const double dlnf = iso ? iso_grad(P, lf, x, y, z, k) : (lf[np] - lf[nm]) / 2.0;
+                    const double dmu = iso ? iso_grad(P, mu, x, y, z, k) : (mu[np] - mu[nm]) / 2.0;
                     double Fk = -rt_i[(long)i * N + n] * (P->RT * dlnf + dmu);
                     if (P->standard_force) {
                         /* eqForceGen: + c_s^2 grad rho_i */
                         const double* ri = rho_i + (long)i * N;
-                        Fk += P->cs2 * (ri[np] - ri[nm]) / 2.0;
+                        Fk += P->cs2 * (iso ? iso_grad(P, ri, x, y, z, k) : (ri[np] - ri[nm]) / 2.0);
                     }
                     force[((long)i * D + k) * N + n] = Fk;
                 }
@@ -361,7 +390,9 @@ int orc_run(const orc_params* P, double* g, double* fprev, long nsteps, long* st
                     const long dx = (k == 0), dy = (k == 1), dz = (k == 2);
                     const double* ri = W.rho_i + (long)i * N;
                     F[k] = W.force[((long)i * D + k) * N + n];
-                    grho[k] = (ri[nidx(P, x + dx, y + dy, z + dz)] - ri[nidx(P, x - dx, y - dy, z - dz)]) / 2.0;
+                    grho[k] = P->stencil == 1
+                                  ? iso_grad(P, ri, x, y, z, k)
+                                  : (ri[nidx(P, x + dx, y + dy, z + dz)] - ri[nidx(P, x - dx, y - dy, z - dz)]) / 2.0;
                 }
                 for (int a = 0; a < Q; ++a) ga[a] = g[((long)i * Q + a) * N + n];
                 orc_equilibrium(P, W.rho_i[(long)i * N + n], u, geq);

@@ -15,9 +15,10 @@ def mixture_of(w, eos=None):
                       kappa=[c["kappa"] for c in comps], eos=eos)
 
 
-def oracle_for(w, eos=None, force_level=0, mrt_S=None, standard_force=False):
+def oracle_for(w, eos=None, force_level=0, mrt_S=None, standard_force=False, stencil="axis"):
     return lbm.OracleLBM(mixture_of(w, eos), w.lattice, w.shape, tau=w.tau, collision=w.collision,
-                         force_level=force_level, mrt_S=mrt_S, standard_force=standard_force)
+                         force_level=force_level, mrt_S=mrt_S, standard_force=standard_force,
+                         stencil=stencil)
 
 
 def direction_map(lattice, gpu_e):
