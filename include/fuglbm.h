@@ -88,7 +88,20 @@ typedef struct fl_component {
  *               FL_FORCE_STANDARD: the standard-LBM form of Sec. V (force
  *               eq. eqForceGen = the fugacity force + c_s^2 grad rho_i, the
  *               standard equilibrium w_a rho_i (1 + e.u/c_s^2 + ...), Guo forcing
- *               without the grad rho_i terms); FP64 populations only */
+ *               without the grad rho_i terms); FP64 populations only
+ *   stencil     FL_STENCIL_AXIS: the central differences of eq1stder and
+ *               eq2ndder along the axes (the paper's); FL_STENCIL_ISOTROPIC:
+ *               the lattice-weighted stencils grad f = (1/c_s^2) sum_a w_a e_a
+ *               f(x + e_a), lap f = (2/c_s^2) sum_a w_a (f(x + e_a) - f(x)),
+ *               equal to the axis ones on fields that vary along one axis and
+ *               stable for 3-D droplets, where the axis ones are not.  With
+ *               them a solver uses the one-thread-per-node collide kernel
+ *               (never the z-marching or one-launch forms); the batched server
+ *               rejects them (FL_EINVAL) */
+/* Stencils of the gradients and Laplacians of steps 6-7 (fl_params.stencil). */
+#define FL_STENCIL_AXIS 0
+#define FL_STENCIL_ISOTROPIC 1
+
 typedef struct fl_params {
     int ncomp;
     const fl_component* comp;
@@ -104,6 +117,7 @@ typedef struct fl_params {
     int precision;
     int force_time_level;
     int force_model;
+    int stencil;
 } fl_params;
 
 typedef struct fl_solver fl_solver;

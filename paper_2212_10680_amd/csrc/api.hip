@@ -189,6 +189,7 @@ int setup(fl_solver* s, const fl_params* p) {
     kp.eos = p->eos;
     kp.force_level = p->force_time_level;
     kp.standard = p->force_model == FL_FORCE_STANDARD ? 1 : 0;
+    kp.iso = p->stencil == FL_STENCIL_ISOTROPIC ? 1 : 0;
     kp.RT = p->R * p->T;
     kp.lnRT = std::log(kp.RT);
     kp.omega = 1.0 / p->tau;
@@ -250,7 +251,7 @@ int setup(fl_solver* s, const fl_params* p) {
         if ((q = std::strstr(t, "zlen=")) && std::sscanf(q + 5, "%d", &v) == 1 && v >= 1 && v <= 4096)
             s->lc.zlen = v;
     }
-    s->zmarch = s->lc.zmarch && fl::zmarch_fits(p->lattice, p->ncomp, p->nx, p->ny);
+    s->zmarch = s->lc.zmarch && p->stencil == FL_STENCIL_AXIS && fl::zmarch_fits(p->lattice, p->ncomp, p->nx, p->ny);
     return FL_OK;
 }
 
@@ -273,7 +274,7 @@ int carve(fl_solver* s, void* base) {
     s->err = (int*)(b + L.err);
     // one-launch step: D3Q19, >= 8 rows per XCD (halo recompute <= 50 %), rows
     // of whole 128-byte lines of the FP64 density arrays, blocks placed on XCD b % 8
-    s->fused = s->lc.fused && s->D == 3 && s->prm.ny >= 64 && s->prm.nx % 16 == 0 && s->prm.nz >= 4 &&
+    s->fused = s->lc.fused && s->kp.iso == 0 && s->D == 3 && s->prm.ny >= 64 && s->prm.nx % 16 == 0 && s->prm.nz >= 4 &&
                xcd_placement_ok(s->stream);
     HIP_TRY(s, hipHostMalloc((void**)&s->h_err, sizeof(int) * 4, hipHostMallocDefault));
     HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
@@ -393,6 +394,7 @@ int fl_validate(const fl_params* p) {
     if (p->force_time_level != 0 && p->force_time_level != 1) return FL_EINVAL;
     if (p->force_model != FL_FORCE_WB && p->force_model != FL_FORCE_STANDARD) return FL_EINVAL;
     if (p->force_model == FL_FORCE_STANDARD && p->precision != FL_FP64) return FL_EINVAL;
+    if (p->stencil != FL_STENCIL_AXIS && p->stencil != FL_STENCIL_ISOTROPIC) return FL_EINVAL;
     if (!(p->tau > 0.5) || !(p->T > 0.0) || !(p->R > 0.0)) return FL_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return FL_EINVAL;
     if (D == 2 && p->nz != 1) return FL_EINVAL;
@@ -831,6 +833,7 @@ int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, vo
     p.nx = p.ny = p.nz = 1;
     const int v = fl_validate(&p);
     if (v != FL_OK) return v;
+    if (p.stencil != FL_STENCIL_AXIS) return FL_EINVAL;  // the server kernel has the axis stencils
     fl_server* s = new (std::nothrow) fl_server();
     if (!s) return FL_ENOMEM;
     setup(&s->cfg, &p);

@@ -20,6 +20,7 @@ struct KParams {
     int eos;
     int force_level;            // 0: previous step's force in u; 1: this step's
     int standard;               // 1: standard-LBM form (eqForceGen), FP64 populations only
+    int iso;                    // 1: isotropic lattice stencils in steps 6-7
     double RT, lnRT;
     double omega;               // 1/tau
     double cF;                  // 1 - 1/(2 tau)

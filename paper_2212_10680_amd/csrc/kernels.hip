@@ -256,6 +256,66 @@ __device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at,
     }
 }
 
+// Steps 6-7 with the isotropic lattice stencils, an option beside the axis
+// differences of eq1stder and eq2ndder (with those, a 3-D sphere leaves the EOS
+// domain; with these it relaxes): with the lattice weights w_a and c_s^2 = 1/3,
+//   grad f(n) = (1/c_s^2) sum_a w_a e_a f(n + e_a),
+//   lap f(n)  = (2/c_s^2) sum_a w_a (f(n + e_a) - f(n)).
+// On a field that varies along one axis only they are the axis differences.
+// Same accessors as stencil_force, phi_at now at offsets e_a + e_b (each
+// coordinate within +-2).
+template <int LAT, int NC, typename T, class PhiAt, class RtAt, class LnfAt>
+__device__ __forceinline__ void stencil_force_iso(const KParams& kp, PhiAt&& phi_at, RtAt&& rt_at, LnfAt&& lnf_at,
+                                                  T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    constexpr double cs2 = 1.0 / 3.0;
+    double mh[Q];  // -lap(phi) at n + e_a
+    mh[0] = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        const double p0 = phi_at(L::ex[a], L::ey[a], L::ez[a]);
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 1; b < Q; ++b)
+            acc += L::w[b] * (phi_at(L::ex[a] + L::ex[b], L::ey[a] + L::ey[b], L::ez[a] + L::ez[b]) - p0);
+        mh[a] = -(2.0 * acc / cs2);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const double rc = rt_at(i, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            F[i][k] = T(0);
+            G[i][k] = T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double sl = 0.0, sm = 0.0, sg = 0.0;
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+                const int e = k == 0 ? L::ex[a] : (k == 1 ? L::ey[a] : L::ez[a]);
+                if (e == 0) continue;
+                const double we = L::w[a] * e;
+                sl += we * lnf_at(i, L::ex[a], L::ey[a], L::ez[a]);
+                sm += we * mh[a];
+                sg += we * rt_at(i, L::ex[a], L::ey[a], L::ez[a]);
+            }
+            const double dl = sl / cs2;
+            const double dm = kp.sk[i] * (sm / cs2);
+            double f = -rc * (kp.RT * dl + dm);
+            const double gr = kp.M[i] * (sg / cs2);
+            if constexpr (sizeof(T) == 8)
+                if (kp.standard) f += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
+            Fs[k] += f;
+            F[i][k] = T(f);
+            G[i][k] = T(gr);
+        }
+    }
+}
+
 // The node's own inputs of steps 8-9: its populations, its rest-population
 // reference (FP32 form) and the previous step's force sum.  With NTLD the
 // populations are loaded with the non-temporal hint: each is read once per
@@ -397,7 +457,7 @@ __device__ __forceinline__ void collide_push(const KParams& kp, const Dims& dm, 
 }
 
 // Steps 6-9 at node n reading the FP64 fields straight from global memory.
-template <int LAT, int NC, typename P, bool MRT, bool NTLD = false>
+template <int LAT, int NC, typename P, bool MRT, bool NTLD = false, bool ISO = false>
 __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dims& dm, int n,
                                                     const P* __restrict__ g, P* __restrict__ gn,
                                                     const float* __restrict__ rref,
@@ -423,14 +483,17 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
     const double* phi = lnf + (size_t)NC * N;
     P F[NC][3], G[NC][3];
     double Fs[3];
-    stencil_force<D, NC, P>(
-        kp, [&](int dx, int dy, int dz) { return phi[idx(dx, dy, dz)]; },
-        [&](int i, int dx, int dy, int dz) { return rt[(size_t)i * N + idx(dx, dy, dz)]; },
-        [&](int i, int dx, int dy, int dz) { return lnf[(size_t)i * N + idx(dx, dy, dz)]; }, F, G, Fs);
+    auto phi_at = [&](int dx, int dy, int dz) { return phi[idx(dx, dy, dz)]; };
+    auto rt_at = [&](int i, int dx, int dy, int dz) { return rt[(size_t)i * N + idx(dx, dy, dz)]; };
+    auto lnf_at = [&](int i, int dx, int dy, int dz) { return lnf[(size_t)i * N + idx(dx, dy, dz)]; };
+    if constexpr (ISO)
+        stencil_force_iso<LAT, NC, P>(kp, phi_at, rt_at, lnf_at, F, G, Fs);
+    else
+        stencil_force<D, NC, P>(kp, phi_at, rt_at, lnf_at, F, G, Fs);
     collide_push<LAT, NC, P, MRT, NTLD>(kp, dm, n, x, y, z, g, gn, rref, F, G, Fs, fsum_in, fsum_out, nt);
 }
 
-template <int LAT, int NC, typename P, bool MRT>
+template <int LAT, int NC, typename P, bool MRT, bool ISO>
 __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __restrict__ g,
                                                         P* __restrict__ gn,
                                                         const float* __restrict__ rref,
@@ -441,7 +504,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
     const int n = slab_order(node_index(xcd_chunk, kp.N, rev != 0), kp.nx, kp.ny, kp.nz, zs);
     if (n < 0) return;
     const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
-    node_collide_stream<LAT, NC, P, MRT, true>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
+    node_collide_stream<LAT, NC, P, MRT, true, ISO>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
 }
 
 // ------------------------------------------------ steps 6-9, z-marching form
@@ -879,14 +942,19 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
     const int rev = lc.reverse_k2 ? 1 : 0;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
-        if (lc.mrt)
-            k_collide_stream<LAT, NC, P, true><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
-                slab_planes(lc, kp));
-        else
-            k_collide_stream<LAT, NC, P, false><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
-                kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
-                slab_planes(lc, kp));
+        auto go = [&](auto mrtc, auto isoc) {
+            k_collide_stream<LAT, NC, P, decltype(mrtc)::value, decltype(isoc)::value>
+                <<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf,
+                                                              (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
+                                                              slab_planes(lc, kp));
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if (lc.mrt) {
+            if (kp.iso) go(T_{}, T_{}); else go(T_{}, F_{});
+        } else {
+            if (kp.iso) go(F_{}, T_{}); else go(F_{}, F_{});
+        }
     });
     return hipGetLastError();
 }

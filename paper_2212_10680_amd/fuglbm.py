@@ -23,6 +23,7 @@ LATTICE = {"D2Q9": 0, "D3Q19": 1}
 COLLISION = {"BGK": 0, "MRT": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 FORCE_MODEL = {"wb": 0, "standard": 1}
+STENCIL = {"axis": 0, "isotropic": 1}
 
 
 class FLError(RuntimeError):
@@ -42,7 +43,7 @@ class fl_params(C.Structure):
         ("T", C.c_double), ("R", C.c_double), ("eos", C.c_int), ("lattice", C.c_int),
         ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("collision", C.c_int),
         ("tau", C.c_double), ("mrt_rates", C.POINTER(C.c_double)), ("precision", C.c_int),
-        ("force_time_level", C.c_int), ("force_model", C.c_int),
+        ("force_time_level", C.c_int), ("force_model", C.c_int), ("stencil", C.c_int),
     ]
 
 
@@ -114,11 +115,12 @@ class Params:
 
     def __init__(self, components, T, shape, lattice="D2Q9", kij=None, R=1.0, eos="PR",
                  collision="BGK", tau=1.0, mrt_rates=None, precision="fp64", force_time_level=0,
-                 force_model="wb"):
+                 force_model="wb", stencil="axis"):
         nc = len(components)
         self._args = dict(components=[dict(c) for c in components], T=T, lattice=lattice, kij=kij, R=R,
                           eos=eos, collision=collision, tau=tau, mrt_rates=mrt_rates,
-                          precision=precision, force_time_level=force_time_level, force_model=force_model)
+                          precision=precision, force_time_level=force_time_level, force_model=force_model,
+                          stencil=stencil)
         self._comp = (fl_component * nc)(*[fl_component(c["Tc"], c["Pc"], c["omega"], c["M"], c["kappa"])
                                            for c in components])
         self._kij = None
@@ -151,6 +153,7 @@ class Params:
         p.precision = PRECISION[precision]
         p.force_time_level = int(force_time_level)
         p.force_model = FORCE_MODEL[force_model]
+        p.stencil = STENCIL[stencil]
         self.c = p
 
     @classmethod

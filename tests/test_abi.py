@@ -61,6 +61,7 @@ def test_validate_accepts_workloads(lib):
     lambda p: setattr(p.c, "precision", 3),
     lambda p: setattr(p.c, "force_time_level", 2),
     lambda p: setattr(p.c, "force_model", 2),
+    lambda p: setattr(p.c, "stencil", 2),
     lambda p: (setattr(p.c, "force_model", 1), setattr(p.c, "precision", 1)),  # standard form: FP64 only
     lambda p: (setattr(p.c, "lattice", 1), setattr(p.c, "nx", 1024), setattr(p.c, "ny", 1024),
                setattr(p.c, "nz", 512)),                                     # 2^29 nodes

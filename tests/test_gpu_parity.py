@@ -25,7 +25,8 @@ def announce(msg):
     print(f"\n[gpu-case] {msg}", flush=True)
 
 
-def make_pair(w, precision="fp64", rho=None, u=None, force_level=0, eos="PR", mrt_rates=None):
+def make_pair(w, precision="fp64", rho=None, u=None, force_level=0, eos="PR", mrt_rates=None,
+              stencil="axis"):
     if rho is None:
         rho, u = wl.initial_field(w)
     nc, D = w.ncomp, w.D
@@ -38,10 +39,10 @@ def make_pair(w, precision="fp64", rho=None, u=None, force_level=0, eos="PR", mr
         table = {"rho": 1.0 / w.tau, "j": mrt_rates[0], "nu": mrt_rates[1], "e": mrt_rates[2],
                  "ghost": mrt_rates[3]}
         S = np.array([table[g] for g in groups])
-    o = oracle_for(w, eos=eos, force_level=force_level, mrt_S=S)
+    o = oracle_for(w, eos=eos, force_level=force_level, mrt_S=S, stencil=stencil)
     o.init(rho, u)
     p = F.Params.from_workload(w, precision=precision, force_time_level=force_level, eos=eos,
-                               mrt_rates=mrt_rates)
+                               mrt_rates=mrt_rates, stencil=stencil)
     s = F.Solver(p)
     s.set_state(rho, u)
     return o, s
@@ -103,6 +104,70 @@ def test_fp64_parity_3d(coll, wname, shape):
         o.run(k)
         s.step(k)
         compare(o, s, w, FP64_BAR, f"3d {coll}")
+
+
+def _sphere(w, shape, R):
+    """Droplet of radius R (tanh profile of width 2) centred in the box."""
+    rL, rV, _ = w.phase_densities()
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2)
+    ind = 0.5 * (1 - np.tanh((r - R) / 2.0))
+    return np.stack([rV[i] + (rL[i] - rV[i]) * ind for i in range(len(rL))]).reshape(len(rL), -1)
+
+
+@pytest.mark.parametrize("coll", ["BGK", "MRT"])
+def test_isotropic_stencils_sphere_vs_oracle(coll):
+    """The isotropic lattice stencils (the option that keeps 3-D droplets in
+    the EOS domain) on a D3Q19 sphere of the benchmark's binary mixture:
+    FP64 element by element against the oracle's isotropic form, on a box
+    that is not a multiple of the z-marching tile in x (so the plain kernel
+    runs either way); the z-marching form is never chosen for them."""
+    shape = (26, 24, 20)
+    w = wl.WORKLOADS["binary_slab_3d"].scaled(shape)
+    w.collision = coll
+    rho = _sphere(w, shape, 6.0)
+    announce(f"isotropic stencils D3Q19 {coll} sphere {shape}")
+    o, s = make_pair(w, rho=rho, stencil="isotropic")
+    for k in (1, 9, 40):
+        o.run(k)
+        s.step(k)
+        compare(o, s, w, FP64_BAR, f"iso 3d {coll}")
+    # a 64 x 4-divisible box would take the z-marching form with the axis
+    # stencils; with the isotropic ones the plain kernel runs
+    w2 = wl.WORKLOADS["binary_slab_3d"].scaled((64, 8, 8))
+    p = F.Params.from_workload(w2, precision="fp32", stencil="isotropic")
+    s2 = F.Solver(p)
+    s2.set_state(*wl.initial_field(w2))
+    names = s2.step_timed(2)
+    assert any("collide_stream" in k for k in names) and not any("zmarch" in k for k in names), names
+
+
+def test_isotropic_stencils_2d_and_fp32():
+    """D2Q9 ternary MRT droplet with the isotropic stencils (FP64, 1e-12), and
+    the FP32-population form on the 3-D sphere (1e-4 of the FP64 oracle)."""
+    w = wl.WORKLOADS["ternary_droplet_2d"].scaled((48, 40))
+    announce("isotropic stencils D2Q9 ternary MRT droplet 48x40")
+    o, s = make_pair(w, stencil="isotropic")
+    for k in (1, 9, 90):
+        o.run(k)
+        s.step(k)
+        compare(o, s, w, FP64_BAR, "iso 2d")
+    shape = (26, 24, 20)
+    w3 = wl.WORKLOADS["binary_slab_3d"].scaled(shape)
+    announce(f"isotropic stencils D3Q19 FP32 sphere {shape}")
+    o, s = make_pair(w3, precision="fp32", rho=_sphere(w3, shape, 6.0), stencil="isotropic")
+    o.run(50)
+    s.step(50)
+    fo, fs = o.fields(), s.fields()
+    assert rel(fs["rho_molar"], fo["rho_molar"]) < FP32_BAR
+
+
+def test_server_rejects_isotropic_stencils():
+    w = wl.WORKLOADS["binary_slab_3d"]
+    p = F.Params.from_workload(w, precision="fp64", stencil="isotropic")
+    with pytest.raises(F.FLError):
+        F.Server(p, 1 << 20)
 
 
 def smooth_vapor_field(w, rho_V, amp=0.05):
