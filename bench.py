@@ -213,6 +213,9 @@ def main():
     ap.add_argument("--state", default="workload", choices=["workload", "uniform"],
                     help="uniform: the workload's mean composition everywhere (a steady state; the "
                          "per-step work does not depend on the state)")
+    ap.add_argument("--stencil", default="axis", choices=["axis", "isotropic"],
+                    help="gradient and Laplacian stencils of the force (isotropic: the lattice-"
+                         "weighted ones that keep 3-D droplets in the EOS domain)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="print the attainable HBM rates of the kernels' access patterns and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -243,7 +246,7 @@ def main():
 
     w = wl.WORKLOADS[args.workload]
     precision = args.precision or w.precision
-    p = F.Params.from_workload(w, precision=precision)
+    p = F.Params.from_workload(w, precision=precision, stencil=args.stencil)
     solver = F.Solver(p)
     rho, u = wl.initial_field(w)
     if args.state == "uniform":
@@ -251,7 +254,8 @@ def main():
                                                    (w.ncomp, w.nodes)))
         u = None
     solver.set_state(rho, u)
-    print(f"[bench] {w.name} {w.lattice} {w.shape} nc={w.ncomp} {w.collision} tau={w.tau} {precision}",
+    print(f"[bench] {w.name} {w.lattice} {w.shape} nc={w.ncomp} {w.collision} tau={w.tau} {precision} "
+          f"{args.stencil} stencils",
           file=sys.stderr, flush=True)
 
     if args.copy_calibration:
@@ -297,7 +301,8 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": stored_traffic(dominant, nodes),
+        # the stored counters were taken with the axis stencils
+        "traffic": stored_traffic(dominant, nodes) if args.stencil == "axis" else None,
         "kernel": dominant,
         "kernel_avg_ms": round(avg_ms, 4),
         "algorithmic_bytes_per_node": ab[dominant],
@@ -321,7 +326,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 populations / f64 EOS" if precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "state": args.state, "lattice": w.lattice, "shape": list(w.shape),
+        "config": {"workload": w.name, "state": args.state, "stencil": args.stencil, "lattice": w.lattice,
+                   "shape": list(w.shape),
                    "ncomp": w.ncomp,
                    "collision": w.collision, "tau": w.tau, "precision": precision,
                    "node_MLUPS": round(nodes * args.steps / wall / 1e6, 1)},

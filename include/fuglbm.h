@@ -95,9 +95,11 @@ typedef struct fl_component {
  *               f(x + e_a), lap f = (2/c_s^2) sum_a w_a (f(x + e_a) - f(x)),
  *               equal to the axis ones on fields that vary along one axis and
  *               stable for 3-D droplets, where the axis ones are not.  With
- *               them a solver uses the one-thread-per-node collide kernel
- *               (never the z-marching or one-launch forms); the batched server
- *               rejects them (FL_EINVAL) */
+ *               them a step is three passes (moments, -lap(phi) at every
+ *               node, then the one-thread-per-node collide kernel; never the
+ *               z-marching or one-launch forms), fl_required_bytes counts one
+ *               more FP64 field, and the batched server rejects them
+ *               (FL_EINVAL) */
 /* Stencils of the gradients and Laplacians of steps 6-7 (fl_params.stencil). */
 #define FL_STENCIL_AXIS 0
 #define FL_STENCIL_ISOTROPIC 1
@@ -166,7 +168,10 @@ int fl_step(fl_solver* s, long nsteps);
 /* Same, but also times each kernel of the step with HIP events on the
  * solver's stream.  kernel_ms[k] receives the summed milliseconds of kernel k
  * over the nsteps steps, names[k] (optional) a static name; *nkernels (in:
- * capacity, out: count). */
+ * capacity, out: count).  The kernels are the moments pass and the collide
+ * pass (2), the one-launch step (1), or with the isotropic stencils the
+ * moments, collide and interface-Laplacian passes (3; FL_EINVAL for a
+ * capacity below the count). */
 int fl_step_timed(fl_solver* s, long nsteps, double* kernel_ms, const char** names,
                   int* nkernels);
 

@@ -102,7 +102,8 @@ Layout layout_for(const fl_params* p) {
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     L.pop = take(2 * nc * Q * N * es);
     L.rt = take(nc * N * 8);
-    L.lnf = take((nc + 1) * N * 8);   // ln f_i, then the interface field phi
+    // ln f_i, then the interface field phi (and -lap(phi) with the isotropic stencils)
+    L.lnf = take((nc + 1 + (p->stencil == FL_STENCIL_ISOTROPIC ? 1 : 0)) * N * 8);
     L.fsum = take(2 * (size_t)D * N * es);
     L.rref = take(p->precision == FL_FP64 ? 0 : nc * N * 4);
     L.snap = take(nc * N * 8);
@@ -320,13 +321,17 @@ int one_step(fl_solver* s, hipEvent_t* ev) {
     } else {
         HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
         if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
+        if (s->kp.iso) {
+            HIP_TRY(s, fl::launch_interface_lap(lc, s->kp, s->lnf));
+            if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
+        }
         if (s->zmarch)
             HIP_TRY(s, fl::launch_collide_zmarch(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
                                                  s->fsum[1 - s->fcur]));
         else
             HIP_TRY(s, fl::launch_collide_stream(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
                                                  s->fsum[1 - s->fcur]));
-        if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
+        if (ev) HIP_TRY(s, hipEventRecord(ev[3], s->stream));
     }
     s->cur = 1 - s->cur;
     s->fcur = 1 - s->fcur;
@@ -539,15 +544,19 @@ int fl_step(fl_solver* s, long nsteps) {
 
 int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms, const char** names,
                         int* nkernels, long* timed_steps) {
-    if (!s || nsteps < 0 || every < 1 || !kernel_ms || !nkernels || *nkernels < 2) return FL_EINVAL;
+    if (!s || nsteps < 0 || every < 1 || !kernel_ms || !nkernels || *nkernels < (s->kp.iso ? 3 : 2))
+        return FL_EINVAL;
     static const char* kNames[2] = {"k_moments_eos", "k_collide_stream"};
     static const char* kFused[1] = {"k_fused_step"};
     const bool fused = s->fused;
+    const bool iso = s->kp.iso != 0;
     const long chunk = 256;
-    // events are created once per solver (creating 768 of them takes
-    // milliseconds, which a timed run should not include)
+    // events are created once per solver (creating 1024 of them takes
+    // milliseconds, which a timed run should not include); per timed step:
+    // start, after the moments pass, after the Laplacian pass (isotropic
+    // stencils), after the collide pass
     if (s->timing_events.empty()) {
-        std::vector<hipEvent_t> made(3 * chunk, nullptr);
+        std::vector<hipEvent_t> made(4 * chunk, nullptr);
         for (auto& e : made) {
             const hipError_t c = hipEventCreate(&e);
             if (c != hipSuccess) {
@@ -559,7 +568,7 @@ int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms
         s->timing_events.swap(made);
     }
     std::vector<hipEvent_t>& ev = s->timing_events;
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     long timed = 0;
     int rc = FL_OK;
     // steps in chunks of `chunk` timed ones (the event pool), then one sync
@@ -567,7 +576,7 @@ int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms
         long j = 0;
         for (; done < nsteps && j < chunk && rc == FL_OK; ++done) {
             if (done % every == 0)
-                rc = one_step(s, &ev[3 * j++]);
+                rc = one_step(s, &ev[4 * j++]);
             else
                 rc = one_step(s, nullptr);
         }
@@ -575,11 +584,18 @@ int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) { rc = hip_fail(s, e, "hipStreamSynchronize"); break; }
         for (long k = 0; k < j; ++k) {
-            float a = 0.f, b = 0.f;
-            (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-            if (!fused) (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+            hipEvent_t* e4 = &ev[4 * k];
+            float a = 0.f, b = 0.f, l = 0.f;
+            (void)hipEventElapsedTime(&a, e4[0], e4[1]);
+            if (!fused && iso) {
+                (void)hipEventElapsedTime(&l, e4[1], e4[2]);
+                (void)hipEventElapsedTime(&b, e4[2], e4[3]);
+            } else if (!fused) {
+                (void)hipEventElapsedTime(&b, e4[1], e4[3]);
+            }
             acc[0] += a;
             acc[1] += b;
+            acc[2] += l;
         }
         timed += j;
     }
@@ -594,6 +610,11 @@ int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms
         kernel_ms[1] = acc[1];
         if (names) { names[0] = kNames[0]; names[1] = s->zmarch ? "k_collide_zmarch" : kNames[1]; }
         *nkernels = 2;
+        if (iso) {
+            kernel_ms[2] = acc[2];
+            if (names) names[2] = "k_interface_lap";
+            *nkernels = 3;
+        }
     }
     return check_err(s);
 }

@@ -262,10 +262,23 @@ __device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at,
 //   grad f(n) = (1/c_s^2) sum_a w_a e_a f(n + e_a),
 //   lap f(n)  = (2/c_s^2) sum_a w_a (f(n + e_a) - f(n)).
 // On a field that varies along one axis only they are the axis differences.
-// Same accessors as stencil_force, phi_at now at offsets e_a + e_b (each
-// coordinate within +-2).
-template <int LAT, int NC, typename T, class PhiAt, class RtAt, class LnfAt>
-__device__ __forceinline__ void stencil_force_iso(const KParams& kp, PhiAt&& phi_at, RtAt&& rt_at, LnfAt&& lnf_at,
+// The Laplacian of phi comes from its own pass (k_interface_lap: a node's
+// gradient of mu_I needs it at all Q-1 neighbours, which would be (Q-1)^2
+// reads of phi here); mh_at(dx,dy,dz) returns -lap(phi) at n + (dx,dy,dz),
+// rt_at and lnf_at as for stencil_force.
+template <int LAT>
+__device__ __forceinline__ double neg_lap_iso(const double* __restrict__ phi, const int (&nb)[Lat<LAT>::Q]) {
+    using L = Lat<LAT>;
+    constexpr double cs2 = 1.0 / 3.0;
+    const double p0 = phi[nb[0]];
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 1; b < L::Q; ++b) acc += L::w[b] * (phi[nb[b]] - p0);
+    return -(2.0 * acc / cs2);
+}
+
+template <int LAT, int NC, typename T, class MhAt, class RtAt, class LnfAt>
+__device__ __forceinline__ void stencil_force_iso(const KParams& kp, MhAt&& mh_at, RtAt&& rt_at, LnfAt&& lnf_at,
                                                   T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
     using L = Lat<LAT>;
     constexpr int D = L::D, Q = L::Q;
@@ -273,14 +286,7 @@ __device__ __forceinline__ void stencil_force_iso(const KParams& kp, PhiAt&& phi
     double mh[Q];  // -lap(phi) at n + e_a
     mh[0] = 0.0;
 #pragma unroll
-    for (int a = 1; a < Q; ++a) {
-        const double p0 = phi_at(L::ex[a], L::ey[a], L::ez[a]);
-        double acc = 0.0;
-#pragma unroll
-        for (int b = 1; b < Q; ++b)
-            acc += L::w[b] * (phi_at(L::ex[a] + L::ex[b], L::ey[a] + L::ey[b], L::ez[a] + L::ez[b]) - p0);
-        mh[a] = -(2.0 * acc / cs2);
-    }
+    for (int a = 1; a < Q; ++a) mh[a] = mh_at(L::ex[a], L::ey[a], L::ez[a]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
 #pragma unroll
@@ -486,11 +492,31 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
     auto phi_at = [&](int dx, int dy, int dz) { return phi[idx(dx, dy, dz)]; };
     auto rt_at = [&](int i, int dx, int dy, int dz) { return rt[(size_t)i * N + idx(dx, dy, dz)]; };
     auto lnf_at = [&](int i, int dx, int dy, int dz) { return lnf[(size_t)i * N + idx(dx, dy, dz)]; };
-    if constexpr (ISO)
-        stencil_force_iso<LAT, NC, P>(kp, phi_at, rt_at, lnf_at, F, G, Fs);
-    else
+    if constexpr (ISO) {
+        const double* mh = phi + N;  // -lap(phi) of k_interface_lap
+        stencil_force_iso<LAT, NC, P>(
+            kp, [&](int dx, int dy, int dz) { return mh[idx(dx, dy, dz)]; }, rt_at, lnf_at, F, G, Fs);
+    } else {
         stencil_force<D, NC, P>(kp, phi_at, rt_at, lnf_at, F, G, Fs);
+    }
     collide_push<LAT, NC, P, MRT, NTLD>(kp, dm, n, x, y, z, g, gn, rref, F, G, Fs, fsum_in, fsum_out, nt);
+}
+
+// -lap(phi) of the isotropic stencils at every node (phi = sum_j sqrt(kappa_j)
+// rho~_j from the moments pass); read by the collide pass at n + e_a.
+template <int LAT>
+__global__ __launch_bounds__(256) void k_interface_lap(const double* __restrict__ phi, double* __restrict__ mh,
+                                                       int nx, int ny, int nz) {
+    using L = Lat<LAT>;
+    const int N = nx * ny * nz;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int x = n % nx, t = n / nx, y = t % ny, z = t / ny;
+    int nb[L::Q];
+#pragma unroll
+    for (int b = 0; b < L::Q; ++b)
+        nb[b] = wrap2(x + L::ex[b], nx) + nx * (wrap2(y + L::ey[b], ny) + ny * wrap2(z + L::ez[b], nz));
+    mh[n] = neg_lap_iso<LAT>(phi, nb);
 }
 
 template <int LAT, int NC, typename P, bool MRT, bool ISO>
@@ -929,6 +955,17 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
         k_moments_eos<LAT, NC, P><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
             kp, (const P*)g, rref, rt, lnf, err, ch, slab_planes(lc, kp));
     });
+    return hipGetLastError();
+}
+
+hipError_t launch_interface_lap(const LaunchCfg& lc, const KParams& kp, double* lnf) {
+    const int nb = (kp.N + 255) / 256;
+    const double* phi = lnf + (size_t)lc.nc * kp.N;
+    double* mh = lnf + (size_t)(lc.nc + 1) * kp.N;
+    if (lc.lattice == 0)
+        k_interface_lap<0><<<nb, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz);
+    else
+        k_interface_lap<1><<<nb, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz);
     return hipGetLastError();
 }
 

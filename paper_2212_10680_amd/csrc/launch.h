@@ -30,6 +30,9 @@ struct LaunchCfg {
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
                               double* rt, double* lnf, int* err);
+// Isotropic stencils only: -lap(phi) at every node into lnf + (N_c + 1) N,
+// from phi at lnf + N_c N (written by launch_moments_eos).
+hipError_t launch_interface_lap(const LaunchCfg& lc, const KParams& kp, double* lnf);
 // fsum_in/fsum_out: force history (population precision), previous and this step
 hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
                                  const float* rref, const double* rt, const double* lnf, const void* fsum_in,

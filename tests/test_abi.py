@@ -99,6 +99,14 @@ def test_required_bytes_scales(lib):
     assert b >= 2 * 2 * 9 * 128 * 8 * 8
 
 
+def test_required_bytes_isotropic_stencils(lib):
+    """The isotropic stencils keep -lap(phi) as one more FP64 field."""
+    w = wl.WORKLOADS["binary_slab_3d"].scaled((64, 32, 16))
+    a = F.Params.from_workload(w, precision="fp32").required_bytes()
+    b = F.Params.from_workload(w, precision="fp32", stencil="isotropic").required_bytes()
+    assert b - a == 64 * 32 * 16 * 8
+
+
 @pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
 def test_lattice_table(lib, name):
     e, w = F.lattice_table(name)
