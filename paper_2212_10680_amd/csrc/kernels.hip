@@ -504,13 +504,15 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
 
 // -lap(phi) of the isotropic stencils at every node (phi = sum_j sqrt(kappa_j)
 // rho~_j from the moments pass); read by the collide pass at n + e_a.
+// Consecutive rows go to one XCD (xcd_chunk), so that the rows y +- 1 a row
+// reads are in that XCD's L2.
 template <int LAT>
 __global__ __launch_bounds__(256) void k_interface_lap(const double* __restrict__ phi, double* __restrict__ mh,
-                                                       int nx, int ny, int nz) {
+                                                       int nx, int ny, int nz, int xcd_chunk) {
     using L = Lat<LAT>;
     const int N = nx * ny * nz;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    const int n = node_index(xcd_chunk, N);
+    if (n < 0) return;
     const int x = n % nx, t = n / nx, y = t % ny, z = t / ny;
     int nb[L::Q];
 #pragma unroll
@@ -960,12 +962,13 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
 
 hipError_t launch_interface_lap(const LaunchCfg& lc, const KParams& kp, double* lnf) {
     const int nb = (kp.N + 255) / 256;
+    const int ch = xcd_chunk_for(lc, nb);
     const double* phi = lnf + (size_t)lc.nc * kp.N;
     double* mh = lnf + (size_t)(lc.nc + 1) * kp.N;
     if (lc.lattice == 0)
-        k_interface_lap<0><<<nb, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz);
+        k_interface_lap<0><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch);
     else
-        k_interface_lap<1><<<nb, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz);
+        k_interface_lap<1><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch);
     return hipGetLastError();
 }
 
