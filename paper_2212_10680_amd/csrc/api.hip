@@ -226,14 +226,18 @@ int setup(fl_solver* s, const fl_params* p) {
     // 4 B per node read and write in longer runs per block (measured:
     // 256^3 ternary 2.32 -> 2.15 ms, 128^3 binary 0.169 -> 0.178 ms the other way).
     s->lc.block_k2 = p->ncomp >= 3 ? 256 : 128;
-    // With the isotropic stencils and N_c >= 3 the collide pass is bound by its
-    // gathers of the stencil fields rather than by the population streams, and
-    // 64-thread blocks are the fastest (256^3 ternary: 3.85 ms at 256, 3.40 at
-    // 128, 3.13 at 64; the binary lattice stays best at 128).
-    if (p->stencil == FL_STENCIL_ISOTROPIC && p->ncomp >= 3) s->lc.block_k2 = 64;
     // ... and takes its blocks in plain order there (2.15 -> 2.09 ms on the
     // 256^3 ternary lattice; the moments pass keeps the XCD-contiguous order).
     s->lc.xcd_remap_k2 = p->ncomp <= 2;
+    // With the isotropic stencils and N_c >= 3 the collide pass is bound by its
+    // re-reads of the stencil fields rather than by the population streams:
+    // 64-thread blocks in XCD-contiguous order are the fastest there (256^3
+    // ternary: 3.85 ms at 256, 3.40 at 128, 3.13 at 64, 3.07 with the XCD
+    // order; the binary lattice stays best at 128).
+    if (p->stencil == FL_STENCIL_ISOTROPIC && p->ncomp >= 3) {
+        s->lc.block_k2 = 64;
+        s->lc.xcd_remap_k2 = true;
+    }
     // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0,rev=1,zmarch=0,zlen=16"
     if (const char* t = std::getenv("FUGLBM_TUNE")) {
         int v;
