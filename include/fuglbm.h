@@ -95,10 +95,12 @@ typedef struct fl_component {
  *               f(x + e_a), lap f = (2/c_s^2) sum_a w_a (f(x + e_a) - f(x)),
  *               equal to the axis ones on fields that vary along one axis and
  *               stable for 3-D droplets, where the axis ones are not.  With
- *               them a step is three passes (moments, -lap(phi) at every
- *               node, then the one-thread-per-node collide kernel; never the
- *               z-marching or one-launch forms), fl_required_bytes counts one
- *               more FP64 field, and the batched server rejects them
+ *               them a step is the moments pass and a z-marching collide pass
+ *               that computes -lap(phi) itself where it fits (D3Q19, N_c <= 3,
+ *               nx % 64 == 0, ny % 4 == 0), otherwise three passes (moments,
+ *               -lap(phi) at every node, one-thread-per-node collide); never
+ *               the one-launch form; fl_required_bytes counts one more FP64
+ *               field, and the batched server rejects them
  *               (FL_EINVAL) */
 /* Stencils of the gradients and Laplacians of steps 6-7 (fl_params.stencil). */
 #define FL_STENCIL_AXIS 0
@@ -126,10 +128,11 @@ typedef struct fl_solver fl_solver;
 
 /* Validate params; FL_EINVAL when ncomp is out of range, tau <= 0.5, a Tc, Pc or
  * M <= 0, a kappa < 0, kij not symmetric or with a non-zero diagonal, a
- * lattice dimension < 1 (or nz != 1 for D2Q9), N = nx*ny*nz >= 2^29 or
- * N * ncomp * (8 for FP64, 4 for FP32 populations) >= 2^32 (every per-array
- * byte offset stays below 2^32), an unknown enum, FL_FORCE_STANDARD with FP32
- * populations. */
+ * lattice dimension < 1 (or nz != 1 for D2Q9), N = nx*ny*nz >= 2^29,
+ * N * ncomp * s >= 2^32 or N * D * s >= 2^32 with s = 8 for FP64 and 4 for
+ * FP32 populations (every per-array byte offset, populations of one direction
+ * and the force history of D values per node included, stays below 2^32), an
+ * unknown enum, FL_FORCE_STANDARD with FP32 populations. */
 int fl_validate(const fl_params* p);
 
 /* Device bytes a solver needs for params (both population buffers, auxiliary
@@ -145,6 +148,26 @@ int fl_create(const fl_params* p, fl_solver** out);
  * NULL for the null stream).  The caller keeps both alive until fl_destroy. */
 int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_stream,
                   fl_solver** out);
+
+/* Launch tuning (kernel variants, block sizes, visiting orders; none of them
+ * changes a result bit).  spec = "key=value[,key=value...]" applied on top of
+ * the measured defaults for the solver's lattice (each call starts from the
+ * defaults; NULL or "" restores them).  Keys: k1block, k2block (threads per
+ * block of the moments and the plain collide pass: 64, 128, 192, 256), remap
+ * (XCD-contiguous block order of both passes, 0/1), remap2 (of the collide
+ * pass only), nt (non-temporal population stores), fused (one-launch step on
+ * D3Q19 lattices with ny >= 64 and nx % 16 == 0, axis stencils), zmarch
+ * (z-marching collide pass where it fits: D3Q19, N_c <= 3, nx % 64 == 0,
+ * ny % 4 == 0; with the isotropic stencils it also computes -lap(phi), so no
+ * Laplacian pass runs), rev (the collide pass sweeps the nodes in the
+ * reverse order), order (y-major rows inside per-XCD z-slabs), zlen (planes
+ * per z-marching workgroup, 1..4096), bands and lapbands (XCD-band order of
+ * the plain collide pass and of the interface-Laplacian pass: the rows of each
+ * plane cut into that many bands, a multiple of 8, each XCD sweeping its bands
+ * along z; 0 = off).  FL_EINVAL (tuning unchanged) for an
+ * unknown key or an out-of-range value.  Synchronises the solver's stream;
+ * takes effect from the next step.  Nothing reads the environment. */
+int fl_set_tuning(fl_solver* s, const char* spec);
 
 void fl_destroy(fl_solver* s);
 const char* fl_last_error(const fl_solver* s);
@@ -238,6 +261,13 @@ int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, vo
 void fl_server_destroy(fl_server* srv);
 const char* fl_server_last_error(const fl_server* srv);
 
+/* Launch tuning of the server kernel, as fl_set_tuning: keys serve (threads
+ * per request workgroup: 256, 512, 1024) and serve_cap (most requests
+ * advanced per tick, oldest first; -1 = as many workgroups as the device holds
+ * at once, 0 = all running).  Results do not depend on either.  FL_EINVAL
+ * (unchanged) for an unknown key or value. */
+int fl_server_set_tuning(fl_server* srv, const char* spec);
+
 /* Pool bytes one request of nx*ny*nz nodes occupies. */
 int fl_server_request_bytes(const fl_server* srv, int nx, int ny, int nz, size_t* bytes);
 
@@ -261,12 +291,17 @@ int fl_server_tick(fl_server* srv, long steps, double max_ms, int* active);
 /* Ids of finished, not yet collected requests (up to cap); *n the count. */
 int fl_server_poll(fl_server* srv, uint64_t* ids, int cap, int* n);
 
-/* Collect a finished request: molar densities [ncomp][N] (may be NULL), steps
- * run, last residual, and its status (FL_OK converged, FL_ENOTCONV max_steps
- * reached, FL_ENUMERIC left the EOS domain).  Frees its slot and memory.
- * FL_EAGAIN if the request is still running, FL_EINVAL for an unknown id. */
-int fl_server_result(fl_server* srv, uint64_t id, double* rho_molar, long* steps, double* residual,
-                     int* status);
+/* Collect a finished request.  Outputs (each may be NULL): rho_molar
+ * [ncomp][N] molar densities (step 2), u [D][N] velocity (step 1, with the
+ * request's stored force of its last step), p [N] EOS pressure (step 4, no
+ * interface term), steps run, last residual, status (FL_OK converged,
+ * FL_ENOTCONV max_steps reached, FL_ENUMERIC left the EOS domain) and
+ * latency_s, the host-clock seconds from the request's admission
+ * (fl_server_submit) to the end of the fl_server_tick that saw it finish.
+ * Frees its slot and memory.  FL_EAGAIN if the request is still running,
+ * FL_EINVAL for an unknown id. */
+int fl_server_result(fl_server* srv, uint64_t id, double* rho_molar, double* u, double* p, long* steps,
+                     double* residual, int* status, double* latency_s);
 
 /* Occupancy: requests in flight, free slots, pool bytes in use and total. */
 int fl_server_info(const fl_server* srv, int* active, int* free_slots, size_t* pool_used,

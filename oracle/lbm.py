@@ -79,11 +79,20 @@ def _load():
         _lib.orc_forcing.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_set_threads.restype = None
+        _lib.orc_iso_stencils.argtypes = [C.POINTER(_Params), dp, dp, dp]
+        _lib.orc_iso_stencils.restype = None
     return _lib
 
 
 def num_threads():
     return _load().orc_num_threads()
+
+
+def set_threads(n):
+    """Host threads the oracle's OpenMP loops use from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def _ptr(a):
@@ -205,6 +214,15 @@ class OracleLBM:
         """[..., N] -> [..., nz, ny, nx] (x fastest)."""
         nx, ny, nz = self.shape
         return f.reshape(f.shape[:-1] + (nz, ny, nx))
+
+    def iso_stencils(self, f):
+        """The isotropic lattice stencils of the scalar field f [N] on this
+        lattice: (grad [D, N], lap [N])."""
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(self.N))
+        grad = np.zeros((3, self.N))
+        lap = np.zeros(self.N)
+        _load().orc_iso_stencils(C.byref(self.params), _ptr(f), _ptr(grad), _ptr(lap))
+        return grad[:self.D], lap
 
     # --------------------------------------------------- single-node pieces
     def eos(self, rho_molar):

@@ -462,3 +462,25 @@ int orc_fields(const orc_params* P, const double* g, const double* fprev, double
     work_free(&W);
     return err;
 }
+
+/* The isotropic stencils of one scalar field f [N] at every node, for checks
+ * of the stencils on their own: grad [3][N] (rows beyond D are zero) and
+ * lap [N]. */
+void orc_iso_stencils(const orc_params* P, const double* f, double* grad, double* lap) {
+    const long N = nnodes(P);
+    for (long n = 0; n < N; ++n) {
+        long x, y, z;
+        ncoord(P, n, &x, &y, &z);
+        for (int k = 0; k < 3; ++k) grad[(long)k * N + n] = k < P->D ? iso_grad(P, f, x, y, z, k) : 0.0;
+        lap[n] = iso_lap(P, f, n, x, y, z);
+    }
+}
+
+/* Host threads of the OpenMP loops (timing on one core, or on all). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

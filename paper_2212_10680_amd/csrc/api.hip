@@ -85,8 +85,6 @@ int lattice_dims(int lattice, int* D, int* Q) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int xcd_placement_ok(hipStream_t stream);
-
 struct Layout {
     size_t pop, rt, lnf, fsum, rref, snap, out, partial, red, err, counters, total;
 };
@@ -161,6 +159,119 @@ bool host_in_domain(const KParams& kp, int nc, const double* rt) {
     return bm * r < 1.0;
 }
 
+// Measured default launch choices for a solver's lattice (kernel variants,
+// block sizes and visiting orders; none of them changes a result bit).
+void default_launch(fl_solver* s) {
+    const fl_params& p = s->prm;
+    LaunchCfg& lc = s->lc;
+    lc.block_k1 = 128;
+    lc.block_k2 = 128;
+    lc.xcd_remap = true;
+    lc.xcd_remap_k2 = true;
+    lc.nt_store = false;
+    lc.fused = false;
+    lc.slab_order = false;
+    lc.zlen = 16;
+    lc.bands = 0;
+    lc.bands_lap = 0;
+    // The collide/stream pass sweeps the nodes in the opposite order to the
+    // moments pass when one population buffer is within a few times the 256 MB
+    // memory-side cache: each pass then starts on the lines the other touched
+    // last.  Larger lattices gain nothing from it.
+    lc.reverse_k2 = (double)s->nc * s->Q * s->N * s->pop_elem <= 1073741824.0;
+    // The z-marching collide kernel (stencil fields staged through LDS) is the
+    // faster one with one or two components; with three and the axis stencils
+    // its registers cost more than the re-reads it saves (measured on the
+    // 256^3 ternary lattice).  With the isotropic stencils the plain kernel's
+    // 18-neighbour gathers of seven FP64 fields set its time, and the
+    // z-marching form (which also computes -lap(phi) itself) is used.
+    lc.zmarch = p.ncomp <= 2 || p.stencil == FL_STENCIL_ISOTROPIC;
+    // Plain collide kernel block size: 128 threads with the interleaved layout
+    // (N_c <= 2), 256 with the component-major one, whose N_c * Q streams of
+    // 4 B per node read and write in longer runs per block (measured:
+    // 256^3 ternary 2.32 -> 2.15 ms, 128^3 binary 0.169 -> 0.178 ms the other way).
+    lc.block_k2 = p.ncomp >= 3 ? 256 : 128;
+    // ... and takes its blocks in plain order there (2.15 -> 2.09 ms on the
+    // 256^3 ternary lattice; the moments pass keeps the XCD-contiguous order).
+    lc.xcd_remap_k2 = p.ncomp <= 2;
+    // With the isotropic stencils and N_c >= 3 the collide pass is bound by its
+    // re-reads of the stencil fields rather than by the population streams:
+    // 64-thread blocks in XCD-contiguous order are the fastest there (256^3
+    // ternary: 3.85 ms at 256, 3.40 at 128, 3.13 at 64, 3.07 with the XCD
+    // order; the binary lattice stays best at 128).
+    if (p.stencil == FL_STENCIL_ISOTROPIC && p.ncomp >= 3) {
+        lc.block_k2 = 64;
+        lc.xcd_remap_k2 = true;
+    }
+}
+
+int xcd_placement_ok(hipStream_t stream);
+
+// Which kernels a step launches, from the launch choices and the lattice.
+void choose_paths(fl_solver* s) {
+    const fl_params& p = s->prm;
+    s->zmarch = s->lc.zmarch && fl::zmarch_fits(p.lattice, p.ncomp, p.nx, p.ny);
+    // one-launch step: D3Q19, >= 8 rows per XCD (halo recompute <= 50 %), rows
+    // of whole 128-byte lines of the FP64 density arrays, blocks placed on XCD b % 8
+    s->fused = s->lc.fused && s->kp.iso == 0 && s->D == 3 && p.ny >= 64 && p.nx % 16 == 0 && p.nz >= 4 &&
+               xcd_placement_ok(s->stream);
+}
+
+// Parses a launch-tuning spec "key=value[,key=value...]" into lc.  Solver
+// keys: k1block, k2block (64..256, multiples of 64), remap, remap2, nt, fused,
+// zmarch, rev, order (0/1), zlen (1..4096); server keys: serve (256, 512,
+// 1024), serve_cap (>= -1).  Returns false (lc unchanged) for an unknown key
+// or an out-of-range value.
+bool parse_tuning(LaunchCfg& lc, const char* spec, bool server) {
+    LaunchCfg t = lc;
+    std::string str(spec);
+    size_t pos = 0;
+    while (pos <= str.size()) {
+        size_t comma = str.find(',', pos);
+        if (comma == std::string::npos) comma = str.size();
+        const std::string item = str.substr(pos, comma - pos);
+        pos = comma + 1;
+        if (item.empty()) continue;
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) return false;
+        const std::string key = item.substr(0, eq);
+        char* endp = nullptr;
+        const long v = std::strtol(item.c_str() + eq + 1, &endp, 10);
+        if (endp == item.c_str() + eq + 1 || *endp != '\0') return false;
+        const bool flag = v == 0 || v == 1;
+        if (!server && (key == "k1block" || key == "k2block")) {
+            if (v < 64 || v > 256 || v % 64) return false;
+            (key == "k1block" ? t.block_k1 : t.block_k2) = (int)v;
+        } else if (!server && key == "remap" && flag) {
+            t.xcd_remap = t.xcd_remap_k2 = v != 0;
+        } else if (!server && key == "remap2" && flag) {
+            t.xcd_remap_k2 = v != 0;
+        } else if (!server && key == "nt" && flag) {
+            t.nt_store = v != 0;
+        } else if (!server && key == "fused" && flag) {
+            t.fused = v != 0;
+        } else if (!server && key == "zmarch" && flag) {
+            t.zmarch = v != 0;
+        } else if (!server && key == "rev" && flag) {
+            t.reverse_k2 = v != 0;
+        } else if (!server && key == "order" && flag) {
+            t.slab_order = v != 0;
+        } else if (!server && key == "zlen" && v >= 1 && v <= 4096) {
+            t.zlen = (int)v;
+        } else if (!server && (key == "bands" || key == "lapbands") && v >= 0 && v <= 1024 && v % 8 == 0) {
+            (key == "bands" ? t.bands : t.bands_lap) = (int)v;
+        } else if (server && key == "serve" && (v == 256 || v == 512 || v == 1024)) {
+            t.serve_block = (int)v;
+        } else if (server && key == "serve_cap" && v >= -1 && v <= 1 << 20) {
+            t.serve_cap = (int)v;
+        } else {
+            return false;
+        }
+    }
+    lc = t;
+    return true;
+}
+
 int setup(fl_solver* s, const fl_params* p) {
     s->prm = *p;
     s->comp.assign(p->comp, p->comp + p->ncomp);
@@ -199,6 +310,18 @@ int setup(fl_solver* s, const fl_params* p) {
     kp.s_nu = s->mrt[1];
     kp.s_e = s->mrt[2];
     kp.s_g = s->mrt[3];
+    {
+        // squared norms of the group rows of the orthogonal moment bases
+        // (Lallemand-Luo D2Q9, d'Humieres D3Q19), in the order of collide()
+        const double dj = kp.s_j - kp.s_g, dn = kp.s_nu - kp.s_g, de = kp.s_e - kp.s_g;
+        if (p->lattice == FL_D2Q9) {
+            const double f[5] = {dj / 6, dj / 6, dn / 4, dn / 4, de / 36};
+            for (int k = 0; k < 5; ++k) kp.mrt_f[k] = f[k];
+        } else {
+            const double f[9] = {dj / 10, dj / 10, dj / 10, dn / 36, dn / 12, dn / 4, dn / 4, dn / 4, de / 2394};
+            for (int k = 0; k < 9; ++k) kp.mrt_f[k] = f[k];
+        }
+    }
     eos_constants(s, &kp);
     s->lc.lattice = p->lattice;
     s->lc.nc = p->ncomp;
@@ -212,56 +335,8 @@ int setup(fl_solver* s, const fl_params* p) {
         s->fc.target = 0;
         s->fc.spin_limit = 1 << 20;   // about 60 ms of s_sleep per wait
     }
-    // The collide/stream pass sweeps the nodes in the opposite order to the
-    // moments pass when one population buffer is within a few times the 256 MB
-    // memory-side cache: each pass then starts on the lines the other touched
-    // last.  Larger lattices gain nothing from it.
-    s->lc.reverse_k2 = (double)s->nc * s->Q * s->N * s->pop_elem <= 1073741824.0;
-    // The z-marching collide kernel (stencil fields staged through LDS) is the
-    // faster one with one or two components; with three its registers cost
-    // more than the re-reads it saves (measured on the 256^3 ternary lattice).
-    s->lc.zmarch = p->ncomp <= 2;
-    // Plain collide kernel block size: 128 threads with the interleaved layout
-    // (N_c <= 2), 256 with the component-major one, whose N_c * Q streams of
-    // 4 B per node read and write in longer runs per block (measured:
-    // 256^3 ternary 2.32 -> 2.15 ms, 128^3 binary 0.169 -> 0.178 ms the other way).
-    s->lc.block_k2 = p->ncomp >= 3 ? 256 : 128;
-    // ... and takes its blocks in plain order there (2.15 -> 2.09 ms on the
-    // 256^3 ternary lattice; the moments pass keeps the XCD-contiguous order).
-    s->lc.xcd_remap_k2 = p->ncomp <= 2;
-    // With the isotropic stencils and N_c >= 3 the collide pass is bound by its
-    // re-reads of the stencil fields rather than by the population streams:
-    // 64-thread blocks in XCD-contiguous order are the fastest there (256^3
-    // ternary: 3.85 ms at 256, 3.40 at 128, 3.13 at 64, 3.07 with the XCD
-    // order; the binary lattice stays best at 128).
-    if (p->stencil == FL_STENCIL_ISOTROPIC && p->ncomp >= 3) {
-        s->lc.block_k2 = 64;
-        s->lc.xcd_remap_k2 = true;
-    }
-    // Launch tuning: FUGLBM_TUNE="k1block=256,k2block=256,remap=1,nt=0,rev=1,zmarch=0,zlen=16"
-    if (const char* t = std::getenv("FUGLBM_TUNE")) {
-        int v;
-        const char* q;
-        if ((q = std::strstr(t, "k1block=")) && std::sscanf(q + 8, "%d", &v) == 1 && v >= 64 && v <= 256 && v % 64 == 0)
-            s->lc.block_k1 = v;
-        if ((q = std::strstr(t, "k2block=")) && std::sscanf(q + 8, "%d", &v) == 1 && v >= 64 && v <= 256 && v % 64 == 0)
-            s->lc.block_k2 = v;
-        if ((q = std::strstr(t, "remap=")) && std::sscanf(q + 6, "%d", &v) == 1)
-            s->lc.xcd_remap = s->lc.xcd_remap_k2 = v != 0;
-        if ((q = std::strstr(t, "remap2=")) && std::sscanf(q + 7, "%d", &v) == 1) s->lc.xcd_remap_k2 = v != 0;
-        if ((q = std::strstr(t, "nt=")) && std::sscanf(q + 3, "%d", &v) == 1) s->lc.nt_store = v != 0;
-        if ((q = std::strstr(t, "serve_cap=")) && std::sscanf(q + 10, "%d", &v) == 1 && v >= -1)
-            s->lc.serve_cap = v;
-        if ((q = std::strstr(t, "serve=")) && std::sscanf(q + 6, "%d", &v) == 1 && (v == 256 || v == 512 || v == 1024))
-            s->lc.serve_block = v;
-        if ((q = std::strstr(t, "fused=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.fused = v != 0;
-        if ((q = std::strstr(t, "zmarch=")) && std::sscanf(q + 7, "%d", &v) == 1) s->lc.zmarch = v != 0;
-        if ((q = std::strstr(t, "rev=")) && std::sscanf(q + 4, "%d", &v) == 1) s->lc.reverse_k2 = v != 0;
-        if ((q = std::strstr(t, "order=")) && std::sscanf(q + 6, "%d", &v) == 1) s->lc.slab_order = v != 0;
-        if ((q = std::strstr(t, "zlen=")) && std::sscanf(q + 5, "%d", &v) == 1 && v >= 1 && v <= 4096)
-            s->lc.zlen = v;
-    }
-    s->zmarch = s->lc.zmarch && p->stencil == FL_STENCIL_AXIS && fl::zmarch_fits(p->lattice, p->ncomp, p->nx, p->ny);
+    default_launch(s);
+    choose_paths(s);
     return FL_OK;
 }
 
@@ -282,10 +357,7 @@ int carve(fl_solver* s, void* base) {
     s->partial = (double*)(b + L.partial);
     s->red = (double*)(b + L.red);
     s->err = (int*)(b + L.err);
-    // one-launch step: D3Q19, >= 8 rows per XCD (halo recompute <= 50 %), rows
-    // of whole 128-byte lines of the FP64 density arrays, blocks placed on XCD b % 8
-    s->fused = s->lc.fused && s->kp.iso == 0 && s->D == 3 && s->prm.ny >= 64 && s->prm.nx % 16 == 0 && s->prm.nz >= 4 &&
-               xcd_placement_ok(s->stream);
+    choose_paths(s);
     HIP_TRY(s, hipHostMalloc((void**)&s->h_err, sizeof(int) * 4, hipHostMallocDefault));
     HIP_TRY(s, hipHostMalloc((void**)&s->h_red, sizeof(double) * 3 * fl::kMaxComp, hipHostMallocDefault));
     HIP_TRY(s, hipMemsetAsync(s->err, 0, 256, s->stream));
@@ -330,11 +402,16 @@ int one_step(fl_solver* s, hipEvent_t* ev) {
     } else {
         HIP_TRY(s, fl::launch_moments_eos(lc, s->kp, g, s->rref, s->rt, s->lnf, s->err));
         if (ev) HIP_TRY(s, hipEventRecord(ev[1], s->stream));
-        if (s->kp.iso) {
+        // the z-marching form computes -lap(phi) itself; the plain kernel reads
+        // it from a pass of its own
+        if (s->kp.iso && !s->zmarch) {
             HIP_TRY(s, fl::launch_interface_lap(lc, s->kp, s->lnf));
             if (ev) HIP_TRY(s, hipEventRecord(ev[2], s->stream));
         }
-        if (s->zmarch)
+        if (s->zmarch && s->kp.iso)
+            HIP_TRY(s, fl::launch_collide_zmarch_iso(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
+                                                     s->fsum[1 - s->fcur]));
+        else if (s->zmarch)
             HIP_TRY(s, fl::launch_collide_zmarch(lc, s->kp, g, gn, s->rref, s->rt, s->lnf, s->fsum[s->fcur],
                                                  s->fsum[1 - s->fcur]));
         else
@@ -414,9 +491,13 @@ int fl_validate(const fl_params* p) {
     if (D == 2 && p->nz != 1) return FL_EINVAL;
     const double N = (double)p->nx * p->ny * p->nz;
     // byte offsets within one array stay below 2^32: the FP64 fields (8 B per
-    // node and component) and one direction's populations (N_c per node)
+    // node and component), one direction's populations (N_c per node) and the
+    // force history (D per node)
     if (N >= 536870912.0) return FL_EINVAL;  // 2^29
-    if (N * p->ncomp * (p->precision == FL_FP64 ? 8.0 : 4.0) >= 4294967296.0) return FL_EINVAL;
+    const double elem = p->precision == FL_FP64 ? 8.0 : 4.0;
+    if (N * p->ncomp * elem >= 4294967296.0) return FL_EINVAL;
+    // ... and the force history fsum[n][k] (D values per node)
+    if (N * D * elem >= 4294967296.0) return FL_EINVAL;
     for (int i = 0; i < p->ncomp; ++i) {
         const fl_component& c = p->comp[i];
         if (!(c.Tc > 0) || !(c.Pc > 0) || !(c.M > 0) || !(c.kappa >= 0) || !std::isfinite(c.omega))
@@ -431,6 +512,23 @@ int fl_validate(const fl_params* p) {
     if (p->collision == FL_MRT && p->mrt_rates)
         for (int k = 0; k < 4; ++k)
             if (!(p->mrt_rates[k] > 0.0 && p->mrt_rates[k] < 2.0)) return FL_EINVAL;
+    return FL_OK;
+}
+
+int fl_set_tuning(fl_solver* s, const char* spec) {
+    if (!s) return FL_EINVAL;
+    const LaunchCfg saved = s->lc;
+    default_launch(s);
+    if (spec && !parse_tuning(s->lc, spec, false)) {
+        s->lc = saved;
+        return fail(s, FL_EINVAL, std::string("unknown tuning key or value in \"") + spec + "\"");
+    }
+    // the one-launch step counts its launches from zeroed plane counters
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->counters, 0, (size_t)8 * s->fc.cstride * sizeof(unsigned), s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->fused_launches = 0;
+    choose_paths(s);
     return FL_OK;
 }
 
@@ -553,12 +651,13 @@ int fl_step(fl_solver* s, long nsteps) {
 
 int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms, const char** names,
                         int* nkernels, long* timed_steps) {
-    if (!s || nsteps < 0 || every < 1 || !kernel_ms || !nkernels || *nkernels < (s->kp.iso ? 3 : 2))
+    if (!s || nsteps < 0 || every < 1 || !kernel_ms || !nkernels ||
+        *nkernels < ((s->kp.iso && !s->zmarch) ? 3 : 2))
         return FL_EINVAL;
     static const char* kNames[2] = {"k_moments_eos", "k_collide_stream"};
     static const char* kFused[1] = {"k_fused_step"};
     const bool fused = s->fused;
-    const bool iso = s->kp.iso != 0;
+    const bool iso = s->kp.iso != 0 && !s->zmarch;   // a Laplacian pass runs
     const long chunk = 256;
     // events are created once per solver (creating 1024 of them takes
     // milliseconds, which a timed run should not include); per timed step:
@@ -617,7 +716,10 @@ int fl_step_timed_every(fl_solver* s, long nsteps, long every, double* kernel_ms
     } else {
         kernel_ms[0] = acc[0];
         kernel_ms[1] = acc[1];
-        if (names) { names[0] = kNames[0]; names[1] = s->zmarch ? "k_collide_zmarch" : kNames[1]; }
+        if (names) {
+            names[0] = kNames[0];
+            names[1] = !s->zmarch ? kNames[1] : s->kp.iso ? "k_collide_zmarch_iso" : "k_collide_zmarch";
+        }
         *nkernels = 2;
         if (iso) {
             kernel_ms[2] = acc[2];
@@ -757,18 +859,31 @@ int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
 }  // extern "C"
 
 // ===================================================================== server
-#include <map>
+#include <chrono>
+
+
+namespace {
+double host_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
 
 struct fl_server {
     fl_solver cfg;                       // parameters, constants and launch config only
     char* pool = nullptr;
     size_t pool_bytes = 0;
-    std::map<size_t, size_t> free_list;  // offset -> size (first fit, merged on free)
+    // free pool ranges (offset, size), sorted by offset, merged on free; at most
+    // one more range than requests in flight, so the capacity reserved at
+    // creation (max_slots + 2) is never exceeded and retiring a request
+    // allocates no host memory either
+    std::vector<std::pair<size_t, size_t>> free_list;
     int max_slots = 0;
     struct Req {
         uint64_t id;
         fl::SlotDesc d;
         size_t off, bytes;
+        double t_submit;                 // host clock (s) when admitted
+        double t_done;                   // end of the tick that saw it finish
     };
     std::vector<Req> reqs;               // running or finished-not-collected
     fl::SlotDesc* d_descs = nullptr;
@@ -813,13 +928,13 @@ ReqLayout req_layout(const fl_solver& c, size_t N) {
 }
 
 bool pool_alloc(fl_server* s, size_t bytes, size_t* off) {
-    for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
-        if (it->second >= bytes) {
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t roff = it->first + bytes;
-            s->free_list.erase(it);
-            if (rest) s->free_list[roff] = rest;
+    for (size_t k = 0; k < s->free_list.size(); ++k) {
+        auto& f = s->free_list[k];
+        if (f.second >= bytes) {
+            *off = f.first;
+            f.first += bytes;
+            f.second -= bytes;
+            if (f.second == 0) s->free_list.erase(s->free_list.begin() + k);
             return true;
         }
     }
@@ -827,18 +942,21 @@ bool pool_alloc(fl_server* s, size_t bytes, size_t* off) {
 }
 
 void pool_free(fl_server* s, size_t off, size_t bytes) {
-    auto it = s->free_list.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != s->free_list.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        s->free_list.erase(nx);
-    }
-    if (it != s->free_list.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-            pv->second += it->second;
-            s->free_list.erase(it);
-        }
+    auto& fl = s->free_list;
+    size_t k = 0;
+    while (k < fl.size() && fl[k].first < off) ++k;
+    const bool join_prev = k > 0 && fl[k - 1].first + fl[k - 1].second == off;
+    const bool join_next = k < fl.size() && off + bytes == fl[k].first;
+    if (join_prev && join_next) {
+        fl[k - 1].second += bytes + fl[k].second;
+        fl.erase(fl.begin() + k);
+    } else if (join_prev) {
+        fl[k - 1].second += bytes;
+    } else if (join_next) {
+        fl[k].first = off;
+        fl[k].second += bytes;
+    } else {
+        fl.insert(fl.begin() + k, {off, bytes});
     }
 }
 
@@ -884,7 +1002,8 @@ int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, vo
         fl_server_destroy(s);
         return FL_ENOMEM;
     }
-    s->free_list[0] = s->pool_bytes;
+    s->free_list.reserve((size_t)max_slots + 2);
+    s->free_list.push_back({0, s->pool_bytes});
     *out = s;
     return FL_OK;
 }
@@ -900,6 +1019,18 @@ void fl_server_destroy(fl_server* s) {
 }
 
 const char* fl_server_last_error(const fl_server* s) { return s ? s->last_error.c_str() : "null server"; }
+
+int fl_server_set_tuning(fl_server* s, const char* spec) {
+    if (!s) return FL_EINVAL;
+    LaunchCfg lc = s->cfg.lc;
+    lc.serve_block = 512;
+    lc.serve_cap = -1;
+    if (spec && !parse_tuning(lc, spec, true))
+        return sfail(s, FL_EINVAL, std::string("unknown tuning key or value in \"") + spec + "\"");
+    SRV_TRY(s, hipStreamSynchronize(s->cfg.stream));
+    s->cfg.lc = lc;
+    return FL_OK;
+}
 
 int fl_server_request_bytes(const fl_server* s, int nx, int ny, int nz, size_t* bytes) {
     if (!s || !bytes || nx < 1 || ny < 1 || nz < 1) return FL_EINVAL;
@@ -961,6 +1092,8 @@ int fl_server_submit(fl_server* s, int nx, int ny, int nz, const double* rho_mol
     r.d.residual = INFINITY;
     r.d.cur = 0;
     r.d.status = fl::kSlotRunning;
+    r.t_submit = host_seconds();
+    r.t_done = 0.0;
     s->reqs.push_back(r);
     *id = r.id;
     return FL_OK;
@@ -1000,7 +1133,11 @@ int fl_server_tick(fl_server* s, long steps, double max_ms, int* active) {
         SRV_TRY(s, fl::launch_serve_tick(lc, s->cfg.kp, s->pool, s->d_descs, n, steps, budget));
         SRV_TRY(s, hipMemcpyAsync(s->h_descs, s->d_descs, sizeof(fl::SlotDesc) * n, hipMemcpyDeviceToHost, lc.stream));
         SRV_TRY(s, hipStreamSynchronize(lc.stream));
-        for (int i = 0; i < n; ++i) s->reqs[run[i]].d = s->h_descs[i];
+        const double now = host_seconds();
+        for (int i = 0; i < n; ++i) {
+            s->reqs[run[i]].d = s->h_descs[i];
+            if (s->h_descs[i].status != fl::kSlotRunning) s->reqs[run[i]].t_done = now;
+        }
     }
     if (active) {
         int a = 0;
@@ -1019,38 +1156,72 @@ int fl_server_poll(fl_server* s, uint64_t* ids, int cap, int* n) {
     return FL_OK;
 }
 
-int fl_server_result(fl_server* s, uint64_t id, double* rho_molar, long* steps, double* residual, int* status) {
-    if (!s) return FL_EINVAL;
-    int k = -1;
+}  // extern "C"
+
+namespace {
+
+// Fields of a finished request into host arrays (any may be NULL), with u and
+// p staged in dev_up ((D + 1) * N doubles of device memory).
+int server_fields(fl_server* s, const fl_server::Req& r, double* dev_up, double* rho_molar, double* u, double* p) {
+    const fl::KParams kp = req_kparams(s, r.d.nx, r.d.ny, r.d.nz);
+    fl::LaunchCfg lc = s->cfg.lc;
+    lc.stream = s->cfg.stream;
+    const size_t N = r.d.N;
+    const int D = s->cfg.D;
+    const float* rref = s->cfg.prm.precision == FL_FP64 ? nullptr : (const float*)(s->pool + r.d.off_rref);
+    hipError_t e = fl::launch_fields(lc, kp, s->pool + r.d.off_pop[r.d.cur], rref, s->pool + r.d.off_fsum,
+                                     (double*)(s->pool + r.d.off_rt), dev_up, dev_up + (size_t)D * N,
+                                     (double*)(s->pool + r.d.off_lnf));
+    if (e == hipSuccess && rho_molar)
+        e = hipMemcpyAsync(rho_molar, s->pool + r.d.off_rt, sizeof(double) * s->cfg.nc * N, hipMemcpyDeviceToHost,
+                           lc.stream);
+    if (e == hipSuccess && u)
+        e = hipMemcpyAsync(u, dev_up, sizeof(double) * D * N, hipMemcpyDeviceToHost, lc.stream);
+    if (e == hipSuccess && p)
+        e = hipMemcpyAsync(p, dev_up + (size_t)D * N, sizeof(double) * N, hipMemcpyDeviceToHost, lc.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(lc.stream);
+    if (e != hipSuccess) return sfail(s, FL_EDEVICE, std::string("result: ") + hipGetErrorString(e));
+    return FL_OK;
+}
+
+// Index of request id among the server's requests, or -1.
+int find_request(const fl_server* s, uint64_t id) {
     for (int i = 0; i < (int)s->reqs.size(); ++i)
-        if (s->reqs[i].id == id) k = i;
-    if (k < 0) return sfail(s, FL_EINVAL, "unknown request id");
-    fl_server::Req r = s->reqs[k];
-    if (r.d.status == fl::kSlotRunning) return FL_EAGAIN;
-    if (rho_molar) {
-        const fl::KParams kp = req_kparams(s, r.d.nx, r.d.ny, r.d.nz);
-        fl::LaunchCfg lc = s->cfg.lc;
-        lc.stream = s->cfg.stream;
-        const size_t N = r.d.N;
-        double* tmp = nullptr;
-        SRV_TRY(s, hipMallocAsync((void**)&tmp, sizeof(double) * (s->cfg.D + 1) * N, lc.stream));
-        const float* rref = s->cfg.prm.precision == FL_FP64 ? nullptr : (const float*)(s->pool + r.d.off_rref);
-        hipError_t e = fl::launch_fields(lc, kp, s->pool + r.d.off_pop[r.d.cur], rref, s->pool + r.d.off_fsum,
-                                         (double*)(s->pool + r.d.off_rt), tmp, tmp + (size_t)s->cfg.D * N,
-                                         (double*)(s->pool + r.d.off_lnf));
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(rho_molar, s->pool + r.d.off_rt, sizeof(double) * s->cfg.nc * N, hipMemcpyDeviceToHost,
-                               lc.stream);
-        (void)hipFreeAsync(tmp, lc.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(lc.stream);
-        if (e != hipSuccess) return sfail(s, FL_EDEVICE, std::string("result: ") + hipGetErrorString(e));
-    }
+        if (s->reqs[i].id == id) return i;
+    return -1;
+}
+
+// Scalar outputs of a finished request, then its slot and memory freed.
+void retire_request(fl_server* s, int k, long* steps, double* residual, int* status, double* latency_s) {
+    const fl_server::Req r = s->reqs[k];
     if (steps) *steps = (long)r.d.steps;
     if (residual) *residual = r.d.residual;
     if (status)
         *status = r.d.status == fl::kSlotConverged ? FL_OK : r.d.status == fl::kSlotMaxSteps ? FL_ENOTCONV : FL_ENUMERIC;
+    if (latency_s) *latency_s = r.t_done - r.t_submit;
     pool_free(s, r.off, r.bytes);
     s->reqs.erase(s->reqs.begin() + k);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fl_server_result(fl_server* s, uint64_t id, double* rho_molar, double* u, double* p, long* steps,
+                     double* residual, int* status, double* latency_s) {
+    if (!s) return FL_EINVAL;
+    const int k = find_request(s, id);
+    if (k < 0) return sfail(s, FL_EINVAL, "unknown request id");
+    const fl_server::Req& r = s->reqs[k];
+    if (r.d.status == fl::kSlotRunning) return FL_EAGAIN;
+    if (rho_molar || u || p) {
+        double* tmp = nullptr;
+        SRV_TRY(s, hipMallocAsync((void**)&tmp, sizeof(double) * (s->cfg.D + 1) * (size_t)r.d.N, s->cfg.stream));
+        const int rc = server_fields(s, r, tmp, rho_molar, u, p);
+        (void)hipFreeAsync(tmp, s->cfg.stream);
+        if (rc != FL_OK) return rc;
+    }
+    retire_request(s, k, steps, residual, status, latency_s);
     return FL_OK;
 }
 

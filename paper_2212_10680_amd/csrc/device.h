@@ -25,6 +25,10 @@ struct KParams {
     double omega;               // 1/tau
     double cF;                  // 1 - 1/(2 tau)
     double s_j, s_nu, s_e, s_g; // MRT rates
+    // (s_k - s_g) / |row k of the moment basis|^2 per group moment, set on the
+    // host for the lattice: D3Q19 jx, jy, jz, then the five stress moments,
+    // then the energy; D2Q9 jx, jy, the two stress moments, the energy
+    double mrt_f[9];
     double b[kMaxComp];
     double M[kMaxComp];
     double aa[kMaxComp * kMaxComp];   // (a alpha)_ij
@@ -250,16 +254,16 @@ __device__ __forceinline__ void collide(const KParams& kp, const CompState<T>& c
                 me += (T(19) * e2 - T(30)) * v[a];
             }
         });
-        // scale by (s_k - s_g) / |row|^2
-        const T dj = T(kp.s_j) - sg, dn = T(kp.s_nu) - sg, de = T(kp.s_e) - sg;
+        // scale by (s_k - s_g) / |row|^2 (per-launch constants)
         if constexpr (L::D == 2) {
-            jx *= dj / T(6); jy *= dj / T(6);
-            m1 *= dn / T(4); m2 *= dn / T(4);
-            me *= de / T(36);
+            jx *= T(kp.mrt_f[0]); jy *= T(kp.mrt_f[1]);
+            m1 *= T(kp.mrt_f[2]); m2 *= T(kp.mrt_f[3]);
+            me *= T(kp.mrt_f[4]);
         } else {
-            jx *= dj / T(10); jy *= dj / T(10); jz *= dj / T(10);
-            m1 *= dn / T(36); m2 *= dn / T(12); m3 *= dn / T(4); m4 *= dn / T(4); m5 *= dn / T(4);
-            me *= de / T(2394);
+            jx *= T(kp.mrt_f[0]); jy *= T(kp.mrt_f[1]); jz *= T(kp.mrt_f[2]);
+            m1 *= T(kp.mrt_f[3]); m2 *= T(kp.mrt_f[4]); m3 *= T(kp.mrt_f[5]); m4 *= T(kp.mrt_f[6]);
+            m5 *= T(kp.mrt_f[7]);
+            me *= T(kp.mrt_f[8]);
         }
         Unroll<0, Q>::run([&](auto ai) {
             constexpr int a = decltype(ai)::value;

@@ -137,6 +137,38 @@ __device__ __forceinline__ int slab_order(int k, int nx, int ny, int nz, int zs)
     return x + nx * (y + ny * z);
 }
 
+// XCD-band visiting order: hardware block b runs on XCD b % 8.  The rows of
+// every plane are cut into `bands` bands (a multiple of 8); XCD k sweeps its
+// bands k, k + 8, ... one after the other, each one plane at a time along z
+// (rows, then x, inside a band-plane; planes downward with rev).  The planes
+// z - 1, z, z + 1 a node's stencil reaches are then the band's last three,
+// whose FP64 fields fit in the XCD's L2, instead of the last three whole
+// planes, which do not.  A bijection of [0, N) for any extents (a band may be
+// empty when ny < bands); -1 for a thread past its band.
+__device__ __forceinline__ int band_node(int nx, int ny, int nz, int bands, bool rev) {
+    const int b = blockIdx.x;
+    const int k = b & 7, j = b >> 3;
+    const int bs = (int)blockDim.x;
+    const int maxrows = (ny + bands - 1) / bands;
+    const int bpp = (maxrows * nx + bs - 1) / bs;   // blocks per band-plane
+    const int m = j / (bpp * nz);                   // which of the XCD's bands
+    if (m >= (bands >> 3)) return -1;
+    const int r = j - m * bpp * nz;
+    int z = r / bpp;
+    const int q = k + 8 * m;
+    const int Y0 = (int)((long long)q * ny / bands), Y1 = (int)((long long)(q + 1) * ny / bands);
+    const int pos = (r - z * bpp) * bs + (int)threadIdx.x;
+    if (pos >= (Y1 - Y0) * nx) return -1;
+    if (rev) z = nz - 1 - z;
+    return pos % nx + nx * (Y0 + pos / nx + ny * z);
+}
+
+// Blocks of a band-ordered launch (see band_node).
+static inline int band_grid(int nx, int ny, int nz, int bands, int bs) {
+    const int maxrows = (ny + bands - 1) / bands;
+    return bands * ((maxrows * nx + bs - 1) / bs) * nz;
+}
+
 // Lattice extent (per solver, or per request in the batched server).
 struct Dims {
     int nx, ny, nz, N;
@@ -262,62 +294,177 @@ __device__ __forceinline__ void stencil_force(const KParams& kp, PhiAt&& phi_at,
 //   grad f(n) = (1/c_s^2) sum_a w_a e_a f(n + e_a),
 //   lap f(n)  = (2/c_s^2) sum_a w_a (f(n + e_a) - f(n)).
 // On a field that varies along one axis only they are the axis differences.
-// The Laplacian of phi comes from its own pass (k_interface_lap: a node's
-// gradient of mu_I needs it at all Q-1 neighbours, which would be (Q-1)^2
-// reads of phi here); mh_at(dx,dy,dz) returns -lap(phi) at n + (dx,dy,dz),
-// rt_at and lnf_at as for stencil_force.
-template <int LAT>
-__device__ __forceinline__ double neg_lap_iso(const double* __restrict__ phi, const int (&nb)[Lat<LAT>::Q]) {
+//
+// -lap(phi) of the isotropic stencil at one point from an accessor
+// phi_at(dx, dy, dz); shared by the Laplacian pass (global memory) and the
+// z-marching collide kernel (LDS), so both give the same bits.
+template <int LAT, class PhiAt>
+__device__ __forceinline__ double neg_lap_iso(PhiAt&& phi_at) {
     using L = Lat<LAT>;
     constexpr double cs2 = 1.0 / 3.0;
-    const double p0 = phi[nb[0]];
+    const double p0 = phi_at(0, 0, 0);
     double acc = 0.0;
 #pragma unroll
-    for (int b = 1; b < L::Q; ++b) acc += L::w[b] * (phi[nb[b]] - p0);
+    for (int b = 1; b < L::Q; ++b) acc = __builtin_fma(L::w[b], phi_at(L::ex[b], L::ey[b], L::ez[b]) - p0, acc);
     return -(2.0 * acc / cs2);
 }
 
-template <int LAT, int NC, typename T, class MhAt, class RtAt, class LnfAt>
-__device__ __forceinline__ void stencil_force_iso(const KParams& kp, MhAt&& mh_at, RtAt&& rt_at, LnfAt&& lnf_at,
-                                                  T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
-    using L = Lat<LAT>;
-    constexpr int D = L::D, Q = L::Q;
-    constexpr double cs2 = 1.0 / 3.0;
-    double mh[Q];  // -lap(phi) at n + e_a
-    mh[0] = 0.0;
-#pragma unroll
-    for (int a = 1; a < Q; ++a) mh[a] = mh_at(L::ex[a], L::ey[a], L::ez[a]);
+// mu_i = RT ln f_i + mu_I,i at one point, mu_I,i = sqrt(kappa_i) (-lap(phi))
+// (steps 5-6): F_i = -rho~_i grad(mu_i) is the force of eqforceFugLBM.
+__device__ __forceinline__ double chem_pot(const KParams& kp, int i, double lnf, double mh) {
+    return __builtin_fma(kp.RT, lnf, kp.sk[i] * mh);
+}
+
+// The D3Q19 isotropic gradient split by planes.  With the weights 1/18 (axis)
+// and 1/36 (edges), grad f(x, y, z) = (1/12) (
+//   x: 2 Ax(z) + Ax(y+1, z) + Ax(y-1, z) + Ax(z+1) + Ax(z-1),
+//   y: 2 Ay(z) + Ay(x+1, z) + Ay(x-1, z) + Ay(z+1) + Ay(z-1),
+//   z: B(z+1) - B(z-1) ),
+// Ax = f(x+1) - f(x-1) and Ay = f(y+1) - f(y-1) in one plane, and B = 2 f +
+// (f(x+1) + f(x-1)) + (f(y+1) + f(y-1)) in one plane.  A node's own plane
+// gives Sx = 2 Ax + (Ax(y+1) + Ax(y-1)) and Sy (its 3 x 3 points); each of the
+// planes z +- 1 gives Ax, Ay and B at the node's column (its cross).  The
+// z-marching kernel computes these from each plane as it passes and keeps
+// them per node, the one-thread-per-node kernel from its neighbours: the same
+// expressions, combined in the same order, give the same bits.
+struct IsoCross {
+    double ax, ay, b;
+};
+struct IsoOwn {
+    double sx, sy, c;
+};
+
+template <class At>
+__device__ __forceinline__ IsoCross iso_cross(At&& f) {
+    IsoCross r;
+    r.ax = f(1, 0) - f(-1, 0);
+    r.ay = f(0, 1) - f(0, -1);
+    const double c = f(0, 0);
+    r.b = (c + c) + ((f(1, 0) + f(-1, 0)) + (f(0, 1) + f(0, -1)));
+    return r;
+}
+
+template <class At>
+__device__ __forceinline__ IsoOwn iso_own(At&& f) {
+    IsoOwn r;
+    const double ax = f(1, 0) - f(-1, 0);
+    const double ay = f(0, 1) - f(0, -1);
+    r.sx = (ax + ax) + ((f(1, 1) - f(-1, 1)) + (f(1, -1) - f(-1, -1)));
+    r.sy = (ay + ay) + ((f(1, 1) - f(1, -1)) + (f(-1, 1) - f(-1, -1)));
+    r.c = f(0, 0);
+    return r;
+}
+
+// Gradient at z from the partial sums Sx(z) + Ax(z-1), Sy(z) + Ay(z-1), the
+// plane below's B and the plane above's cross (times 1/12 rounded, not a
+// division: a multiply instead of a division sequence in FP64).
+__device__ __forceinline__ void iso_grad(double px, double py, double bm, const IsoCross& up, double (&g)[3]) {
+    constexpr double kTwelfth = 1.0 / 12.0;
+    g[0] = (px + up.ax) * kTwelfth;
+    g[1] = (py + up.ay) * kTwelfth;
+    g[2] = (up.b - bm) * kTwelfth;
+}
+
+// F_i = -rho~_i grad(mu_i), grad rho_i = M_i grad(rho~_i) (step 7), from the
+// gradients of mu_i and rho~_i and the node's rho~_i, kept in the collision
+// precision T; their sum over components in FP64.
+template <int NC, typename T>
+__device__ __forceinline__ void force_from_grads(const KParams& kp, const double (&gmu)[NC][3],
+                                                 const double (&grt)[NC][3], const double (&rc)[NC],
+                                                 T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const double rc = rt_at(i, 0, 0, 0);
+    for (int i = 0; i < NC; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            F[i][k] = T(0);
-            G[i][k] = T(0);
-        }
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double sl = 0.0, sm = 0.0, sg = 0.0;
-#pragma unroll
-            for (int a = 1; a < Q; ++a) {
-                const int e = k == 0 ? L::ex[a] : (k == 1 ? L::ey[a] : L::ez[a]);
-                if (e == 0) continue;
-                const double we = L::w[a] * e;
-                sl += we * lnf_at(i, L::ex[a], L::ey[a], L::ez[a]);
-                sm += we * mh[a];
-                sg += we * rt_at(i, L::ex[a], L::ey[a], L::ez[a]);
-            }
-            const double dl = sl / cs2;
-            const double dm = kp.sk[i] * (sm / cs2);
-            double f = -rc * (kp.RT * dl + dm);
-            const double gr = kp.M[i] * (sg / cs2);
+            double f = -(rc[i] * gmu[i][k]);
+            const double gr = kp.M[i] * grt[i][k];
             if constexpr (sizeof(T) == 8)
                 if (kp.standard) f += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
             Fs[k] += f;
             F[i][k] = T(f);
             G[i][k] = T(gr);
+        }
+}
+
+// Steps 6-7 at one node of a D3Q19 lattice with the isotropic stencils, from
+// accessors mu_at(i, dx, dy, dz) of mu_i and rt_at(i, dx, dy, dz) of rho~_i at
+// the node's D3Q19 neighbours: the gradients by planes (iso_own at the node's
+// plane, iso_cross at the planes below and above), then the forces.
+// With SERIAL, the instruction scheduler may not move work across components
+// (it would otherwise issue every component's stencil reads at once, which
+// costs registers); the arithmetic is the same either way.
+template <int NC, typename T, bool SERIAL = false, class MuAt, class RtAt>
+__device__ __forceinline__ void stencil_force_iso_mu(const KParams& kp, MuAt&& mu_at, RtAt&& rt_at, T (&F)[NC][3],
+                                                     T (&G)[NC][3], double (&Fs)[3]) {
+    double gmu[NC][3], grt[NC][3], rc[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        if constexpr (SERIAL) __builtin_amdgcn_sched_barrier(0);
+        auto mu = [&](int dz) { return [&, dz](int dx, int dy) { return mu_at(i, dx, dy, dz); }; };
+        auto r = [&](int dz) { return [&, dz](int dx, int dy) { return rt_at(i, dx, dy, dz); }; };
+        const IsoCross mdn = iso_cross(mu(-1)), mup = iso_cross(mu(1));
+        const IsoOwn mown = iso_own(mu(0));
+        iso_grad(mown.sx + mdn.ax, mown.sy + mdn.ay, mdn.b, mup, gmu[i]);
+        const IsoCross rdn = iso_cross(r(-1)), rup = iso_cross(r(1));
+        const IsoOwn rown = iso_own(r(0));
+        iso_grad(rown.sx + rdn.ax, rown.sy + rdn.ay, rdn.b, rup, grt[i]);
+        rc[i] = rown.c;
+    }
+    force_from_grads<NC, T>(kp, gmu, grt, rc, F, G, Fs);
+}
+
+// Steps 6-7 at one node with the isotropic stencils, from accessors of the
+// fields of the moments pass: mh_at(dx,dy,dz) = -lap(phi) (from the Laplacian
+// pass), rt_at and lnf_at as for stencil_force.
+template <int LAT, int NC, typename T, class MhAt, class RtAt, class LnfAt>
+__device__ __forceinline__ void stencil_force_iso(const KParams& kp, MhAt&& mh_at, RtAt&& rt_at, LnfAt&& lnf_at,
+                                                  T (&F)[NC][3], T (&G)[NC][3], double (&Fs)[3]) {
+    using L = Lat<LAT>;
+    constexpr int D = L::D, Q = L::Q;
+    if constexpr (D == 3) {
+        stencil_force_iso_mu<NC, T>(
+            kp, [&](int i, int dx, int dy, int dz) { return chem_pot(kp, i, lnf_at(i, dx, dy, dz), mh_at(dx, dy, dz)); },
+            rt_at, F, G, Fs);
+    } else {
+        constexpr double cs2 = 1.0 / 3.0;
+        double mh[Q];  // -lap(phi) at n + e_a
+        mh[0] = 0.0;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) mh[a] = mh_at(L::ex[a], L::ey[a], L::ez[a]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const double rc = rt_at(i, 0, 0, 0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                F[i][k] = T(0);
+                G[i][k] = T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double sl = 0.0, sm = 0.0, sg = 0.0;
+#pragma unroll
+                for (int a = 1; a < Q; ++a) {
+                    const int e = k == 0 ? L::ex[a] : (k == 1 ? L::ey[a] : L::ez[a]);
+                    if (e == 0) continue;
+                    const double we = L::w[a] * e;
+                    sl += we * lnf_at(i, L::ex[a], L::ey[a], L::ez[a]);
+                    sm += we * mh[a];
+                    sg += we * rt_at(i, L::ex[a], L::ey[a], L::ez[a]);
+                }
+                const double dl = sl / cs2;
+                const double dm = kp.sk[i] * (sm / cs2);
+                double f = -rc * (kp.RT * dl + dm);
+                const double gr = kp.M[i] * (sg / cs2);
+                if constexpr (sizeof(T) == 8)
+                    if (kp.standard) f += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
+                Fs[k] += f;
+                F[i][k] = T(f);
+                G[i][k] = T(gr);
+            }
         }
     }
 }
@@ -508,17 +655,14 @@ __device__ __forceinline__ void node_collide_stream(const KParams& kp, const Dim
 // reads are in that XCD's L2.
 template <int LAT>
 __global__ __launch_bounds__(256) void k_interface_lap(const double* __restrict__ phi, double* __restrict__ mh,
-                                                       int nx, int ny, int nz, int xcd_chunk) {
-    using L = Lat<LAT>;
+                                                       int nx, int ny, int nz, int xcd_chunk, int bands) {
     const int N = nx * ny * nz;
-    const int n = node_index(xcd_chunk, N);
+    const int n = bands > 0 ? band_node(nx, ny, nz, bands, false) : node_index(xcd_chunk, N);
     if (n < 0) return;
     const int x = n % nx, t = n / nx, y = t % ny, z = t / ny;
-    int nb[L::Q];
-#pragma unroll
-    for (int b = 0; b < L::Q; ++b)
-        nb[b] = wrap2(x + L::ex[b], nx) + nx * (wrap2(y + L::ey[b], ny) + ny * wrap2(z + L::ez[b], nz));
-    mh[n] = neg_lap_iso<LAT>(phi, nb);
+    mh[n] = neg_lap_iso<LAT>([&](int dx, int dy, int dz) {
+        return phi[wrap2(x + dx, nx) + nx * (wrap2(y + dy, ny) + ny * wrap2(z + dz, nz))];
+    });
 }
 
 template <int LAT, int NC, typename P, bool MRT, bool ISO>
@@ -528,8 +672,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(KParams kp, const P* __r
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
                                                         const P* fsum_in, P* fsum_out, int xcd_chunk, int nt,
-                                                        int rev, int zs) {
-    const int n = slab_order(node_index(xcd_chunk, kp.N, rev != 0), kp.nx, kp.ny, kp.nz, zs);
+                                                        int rev, int zs, int bands) {
+    const int n = bands > 0 ? band_node(kp.nx, kp.ny, kp.nz, bands, rev != 0)
+                            : slab_order(node_index(xcd_chunk, kp.N, rev != 0), kp.nx, kp.ny, kp.nz, zs);
     if (n < 0) return;
     const Dims dm{kp.nx, kp.ny, kp.nz, kp.N};
     node_collide_stream<LAT, NC, P, MRT, true, ISO>(kp, dm, n, g, gn, rref, rt, lnf, fsum_in, fsum_out, nt != 0);
@@ -713,6 +858,167 @@ __global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(K
 #pragma unroll
             for (int k = 0; k < kRlPer; ++k)
                 if (rl_fills(k)) s_rl[(it + 1) & 1][f][t + 256 * k] = frl[f][k];
+        __syncthreads();
+    }
+}
+
+// ------------------------- steps 6-9, z-marching form, isotropic stencils
+// D3Q19.  A 256-thread workgroup owns a kZX x kZY tile of (x, y) and sweeps the
+// planes z0 .. z1-1 of its z-range upward; no Laplacian pass runs before it.
+// LDS holds
+//   phi          four planes (tile + halo 2) in a ring;
+//   mu_i, rho~_i three planes (tile + halo 1) in three buffers, plane q in
+//                buffer q mod 3: mu_i = RT ln f_i + sqrt(kappa_i) (-lap(phi))
+//                is formed as a plane is filled, -lap(phi) from the phi ring.
+// Node z reads mu_i and rho~_i of planes z-1, z, z+1 from LDS with the
+// stencil of the one-thread-per-node kernel (stencil_force_iso_mu), so the
+// result is the same bit for bit.  Per node plane z, two barriers: after the
+// stencil reads (plane z-1's buffer is then refilled with plane z+2, and the
+// phi slot of plane z with plane z+4), and at the end.  Planes z0-1 .. z1 of
+// mu_i and rho~_i and z0-2 .. z1+1 of phi pass through a workgroup.
+template <int NC, typename P>
+constexpr int kZmarchIsoWaves = sizeof(P) == 4 ? 2 : 1;
+
+__device__ __forceinline__ int mod3(int q) { return ((q % 3) + 3) % 3; }
+
+template <int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarch_iso(
+    KParams kp, const P* __restrict__ g, P* __restrict__ gn, const float* __restrict__ rref,
+    const double* __restrict__ rt, const double* __restrict__ lnf, const P* fsum_in, P* fsum_out, int zlen,
+    int xcd_chunk, int nt) {
+    constexpr int NF = 2 * NC;  // fields: mu_i, then rho~_i
+    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const size_t N = kp.N;
+    const int plane = nx * ny;
+    const int tiles_x = nx / kZX;
+    const int tiles_xy = tiles_x * (ny / kZY);
+    const int nzc = (nz + zlen - 1) / zlen;
+    const int b = blockIdx.x;
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
+    const int zc = lb / tiles_xy, txy = lb - zc * tiles_xy;
+    const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
+    const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
+    const int t = threadIdx.x;
+    const int tx = t % kZX, ty = t / kZX;
+    const int x = x0 + tx, y = y0 + ty;
+    const int col = x + nx * y;
+    const Dims dm{nx, ny, nz, kp.N};
+    const double* phig = lnf + (size_t)NC * N;
+
+    __shared__ double s_phi[4][kPhiPts];   // phi plane q in slot q & 3
+    __shared__ double s_f[3][NF][kRlPts];  // mu_i, rho~_i of plane q in buffer q mod 3
+
+    // fill pattern, the same for every plane (points past the box read offset 0
+    // and are not stored)
+    unsigned phi_off[kPhiPer], rl_off[kRlPer];
+#pragma unroll
+    for (int k = 0; k < kPhiPer; ++k) {
+        const int q = t + 256 * k;
+        phi_off[k] = q < kPhiPts ? 8u * (unsigned)(wrap2(x0 - 2 + q % kPhiW, nx) + nx * wrap2(y0 - 2 + q / kPhiW, ny)) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kRlPer; ++k) {
+        const int q = t + 256 * k;
+        rl_off[k] = q < kRlPts ? 8u * (unsigned)(wrap2(x0 - 1 + q % kRlW, nx) + nx * wrap2(y0 - 1 + q / kRlW, ny)) : 0u;
+    }
+    auto phi_fills = [&](int k) { return k < kPhiPer - 1 || t + 256 * k < kPhiPts; };
+    auto rl_fills = [&](int k) { return k < kRlPer - 1 || t + 256 * k < kRlPts; };
+    auto zoff = [&](int zz) { return (size_t)wrap2(zz, nz) * plane; };
+    // ln f_i (f < NC) and rho~_i (f >= NC) of the moments pass
+    auto src_of = [&](int f) { return f < NC ? lnf + (size_t)f * N : rt + (size_t)(f - NC) * N; };
+
+    auto load_phi = [&](int q, double (&v)[kPhiPer]) {
+        const double* src = phig + zoff(q);
+#pragma unroll
+        for (int k = 0; k < kPhiPer; ++k) v[k] = ld(src, phi_off[k]);
+    };
+    auto store_phi = [&](int q, const double (&v)[kPhiPer]) {
+#pragma unroll
+        for (int k = 0; k < kPhiPer; ++k)
+            if (phi_fills(k)) s_phi[q & 3][t + 256 * k] = v[k];
+    };
+    // ln f_i and rho~_i of plane q at this thread's fill points
+    auto load_fill = [&](int q, double (&v)[NF][kRlPer]) {
+        const size_t zo = zoff(q);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int k = 0; k < kRlPer; ++k) v[f][k] = ld(src_of(f) + zo, rl_off[k]);
+    };
+    // mu_i and rho~_i of plane q into its buffer (phi planes q-1 .. q+1 in the ring)
+    auto store_fill = [&](int q, const double (&v)[NF][kRlPer]) {
+        const int bq = mod3(q);
+#pragma unroll
+        for (int k = 0; k < kRlPer; ++k) {
+            if (!rl_fills(k)) continue;
+            const int pt = t + 256 * k;
+            const int bx = pt % kRlW + 1, by = pt / kRlW + 1;  // in the phi box
+            const double mh = neg_lap_iso<1>([&](int dx, int dy, int dz) {
+                return s_phi[(q + dz) & 3][(by + dy) * kPhiW + bx + dx];
+            });
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                s_f[bq][i][pt] = chem_pot(kp, i, v[i][k], mh);
+                s_f[bq][NC + i][pt] = v[NC + i][k];
+            }
+        }
+    };
+
+    // prologue: phi planes z0-2 .. z0+1; mu_i, rho~_i of planes z0-1 and z0;
+    // phi planes z0+2, z0+3 into the slots of z0-2, z0-1; then plane z0+1
+    {
+        double v[NF][kRlPer], w[NF][kRlPer], fp[kPhiPer];
+#pragma unroll
+        for (int d = -2; d <= 1; ++d) {
+            load_phi(z0 + d, fp);
+            store_phi(z0 + d, fp);
+        }
+        load_fill(z0 - 1, v);
+        load_fill(z0, w);
+        __syncthreads();
+        store_fill(z0 - 1, v);
+        store_fill(z0, w);
+        load_fill(z0 + 1, v);
+        __syncthreads();
+        load_phi(z0 + 2, fp);
+        store_phi(z0 + 2, fp);
+        load_phi(z0 + 3, fp);
+        store_phi(z0 + 3, fp);
+        __syncthreads();
+        store_fill(z0 + 1, v);
+        __syncthreads();
+    }
+
+    const int cown = (ty + 1) * kRlW + tx + 1;
+    for (int z = z0; z < z1; ++z) {
+        const bool fill = z + 2 <= z1;   // plane z+2 is needed (by node z+1)
+        const bool ring = z + 3 <= z1;   // phi plane z+4 is needed (for plane z+3)
+        // loads first: plane z+2's fields, phi plane z+4 (their latency
+        // overlaps the stencil)
+        double v[NF][kRlPer], fp[kPhiPer];
+        if (fill) load_fill(z + 2, v);
+        if (ring) load_phi(z + 4, fp);
+        __builtin_amdgcn_sched_barrier(0);
+
+        // node z's stencil: mu_i and rho~_i of planes z-1, z, z+1
+        P F[NC][3], G[NC][3];
+        double Fs[3];
+        const int bm = mod3(z - 1), b0 = mod3(z), bp = mod3(z + 1);
+        auto buf = [&](int dz) { return dz < 0 ? bm : (dz > 0 ? bp : b0); };
+        stencil_force_iso_mu<NC, P, true>(
+            kp, [&](int i, int dx, int dy, int dz) { return s_f[buf(dz)][i][cown + dy * kRlW + dx]; },
+            [&](int i, int dx, int dy, int dz) { return s_f[buf(dz)][NC + i][cown + dy * kRlW + dx]; }, F, G,
+            Fs);
+        // node z's inputs (their latency overlaps the barrier and the fill)
+        NodeIn<1, NC, P> in;
+        load_node_inputs<1, NC, P, true>(g, fsum_in, rref, col + z * plane, N, in);
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();  // plane z-1's buffer and phi slot z are free
+
+        if (fill) store_fill(z + 2, v);
+        if (ring) store_phi(z + 4, fp);
+        collide_push_loaded<1, NC, P, MRT>(kp, dm, col + z * plane, x, y, z, in, gn, F, G, Fs, fsum_out, nt != 0);
         __syncthreads();
     }
 }
@@ -963,12 +1269,14 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
 hipError_t launch_interface_lap(const LaunchCfg& lc, const KParams& kp, double* lnf) {
     const int nb = (kp.N + 255) / 256;
     const int ch = xcd_chunk_for(lc, nb);
+    const int bands = lc.bands_lap;
+    const dim3 grid = bands > 0 ? dim3(band_grid(kp.nx, kp.ny, kp.nz, bands, 256)) : grid_remapped(nb, ch);
     const double* phi = lnf + (size_t)lc.nc * kp.N;
     double* mh = lnf + (size_t)(lc.nc + 1) * kp.N;
     if (lc.lattice == 0)
-        k_interface_lap<0><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch);
+        k_interface_lap<0><<<grid, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch, bands);
     else
-        k_interface_lap<1><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch);
+        k_interface_lap<1><<<grid, 256, 0, lc.stream>>>(phi, mh, kp.nx, kp.ny, kp.nz, ch, bands);
     return hipGetLastError();
 }
 
@@ -980,13 +1288,14 @@ hipError_t launch_collide_stream(const LaunchCfg& lc, const KParams& kp, const v
     const int ch = lc.xcd_remap_k2 ? xcd_chunk_for(lc, nb) : 0;
     const int nt = lc.nt_store ? 1 : 0;
     const int rev = lc.reverse_k2 ? 1 : 0;
+    const int bands = lc.bands;
+    const dim3 grid = bands > 0 ? dim3(band_grid(kp.nx, kp.ny, kp.nz, bands, bs)) : grid_remapped(nb, ch);
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         auto go = [&](auto mrtc, auto isoc) {
             k_collide_stream<LAT, NC, P, decltype(mrtc)::value, decltype(isoc)::value>
-                <<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf,
-                                                              (const P*)fsum_in, (P*)fsum_out, ch, nt, rev,
-                                                              slab_planes(lc, kp));
+                <<<grid, bs, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in,
+                                             (P*)fsum_out, ch, nt, rev, slab_planes(lc, kp), bands);
         };
         using T_ = std::true_type;
         using F_ = std::false_type;
@@ -1027,6 +1336,27 @@ hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const v
             } else {
                 if (lc.reverse_k2) go(std::false_type{}, Down{}); else go(std::false_type{}, Up{});
             }
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_zmarch_iso(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                     const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                     void* fsum_out) {
+    if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1) return hipErrorInvalidValue;
+    const int nb = (kp.nx / kZX) * (kp.ny / kZY) * ((kp.nz + lc.zlen - 1) / lc.zlen);
+    const int ch = xcd_chunk_for(lc, nb);
+    const int nt = lc.nt_store ? 1 : 0;
+    dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
+        FL_TYPES;
+        if constexpr (LAT == 1 && NC <= 3) {
+            if (lc.mrt)
+                k_collide_zmarch_iso<NC, P, true><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+            else
+                k_collide_zmarch_iso<NC, P, false><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
         }
     });
     return hipGetLastError();

@@ -21,11 +21,14 @@ struct LaunchCfg {
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
     int serve_cap = -1;     // most requests advanced per tick, oldest first
                             // (-1: as many as the device holds at once, 0: all running)
-    bool fused = false;     // one-launch step (FUGLBM_TUNE fused=1) when the lattice allows it
+    bool fused = false;     // one-launch step (fl_set_tuning "fused=1") when the lattice allows it
     bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (set per solver)
     bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
-    bool slab_order = false;  // y-major row order inside per-XCD z-slabs (FUGLBM_TUNE order=1)
+    bool slab_order = false;  // y-major row order inside per-XCD z-slabs (fl_set_tuning "order=1")
     int zlen = 16;          // planes per workgroup of the z-marching kernel
+    int bands = 0;          // XCD-band order of the plain collide pass (band_node): row bands, a
+                            // multiple of 8; 0 = off
+    int bands_lap = 0;      // the same for the interface-Laplacian pass
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
@@ -56,6 +59,11 @@ bool zmarch_fits(int lattice, int nc, int nx, int ny);
 hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
                                  const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                  void* fsum_out);
+// The same with the isotropic stencils (kp.iso): -lap(phi) is computed from
+// phi inside the pass, so no Laplacian pass runs before it.
+hipError_t launch_collide_zmarch_iso(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
+                                     const float* rref, const double* rt, const double* lnf, const void* fsum_in,
+                                     void* fsum_out);
 hipError_t launch_init(const LaunchCfg& lc, const KParams& kp, const double* rho_molar, const double* u,
                        void* g, float* rref, void* fsum);
 hipError_t launch_fields(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,

@@ -58,6 +58,7 @@ SIGNATURES = {
     "fl_create": (C.c_int, [C.POINTER(fl_params), C.POINTER(_VP)]),
     "fl_create_ext": (C.c_int, [C.POINTER(fl_params), _VP, C.c_size_t, _VP, C.POINTER(_VP)]),
     "fl_destroy": (None, [_VP]),
+    "fl_set_tuning": (C.c_int, [_VP, C.c_char_p]),
     "fl_last_error": (C.c_char_p, [_VP]),
     "fl_status_string": (C.c_char_p, [C.c_int]),
     "fl_lattice_table": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _DP]),
@@ -76,13 +77,15 @@ SIGNATURES = {
     "fl_set_state_raw": (C.c_int, [_VP, _VP, C.c_size_t]),
     "fl_server_create": (C.c_int, [C.POINTER(fl_params), C.c_size_t, C.c_int, _VP, C.POINTER(_VP)]),
     "fl_server_destroy": (None, [_VP]),
+    "fl_server_set_tuning": (C.c_int, [_VP, C.c_char_p]),
     "fl_server_last_error": (C.c_char_p, [_VP]),
     "fl_server_request_bytes": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "fl_server_submit": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _DP, C.c_double, C.c_long, C.c_long,
                                    C.POINTER(C.c_uint64)]),
     "fl_server_tick": (C.c_int, [_VP, C.c_long, C.c_double, C.POINTER(C.c_int)]),
     "fl_server_poll": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int, C.POINTER(C.c_int)]),
-    "fl_server_result": (C.c_int, [_VP, C.c_uint64, _DP, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int)]),
+    "fl_server_result": (C.c_int, [_VP, C.c_uint64, _DP, _DP, _DP, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int),
+                                   _DP]),
     "fl_server_info": (C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
                                  C.POINTER(C.c_size_t)]),
 }
@@ -235,6 +238,11 @@ class Solver:
             pass
 
     # ---------------------------------------------------------------- calls
+    def set_tuning(self, spec=None):
+        """Launch tuning on top of the measured defaults (fl_set_tuning)."""
+        arg = None if spec is None else spec.encode()
+        self._check(self.lib.fl_set_tuning(self.h, arg), "fl_set_tuning")
+
     def set_state(self, rho_molar, u=None):
         p = self.p
         r = np.ascontiguousarray(np.asarray(rho_molar, dtype=np.float64).reshape(p.ncomp, p.N))
@@ -342,6 +350,11 @@ class Server:
         except Exception:
             pass
 
+    def set_tuning(self, spec=None):
+        """Server launch tuning (fl_server_set_tuning): serve, serve_cap."""
+        arg = None if spec is None else spec.encode()
+        self._check(self.lib.fl_server_set_tuning(self.h, arg), "fl_server_set_tuning")
+
     def request_bytes(self, shape):
         nx, ny, nz = (tuple(shape) + (1,))[:3]
         b = C.c_size_t(0)
@@ -375,13 +388,21 @@ class Server:
         self._check(self.lib.fl_server_poll(self.h, ids, cap, C.byref(n)), "fl_server_poll")
         return [ids[i] for i in range(n.value)]
 
-    def result(self, rid, n_nodes):
+    def result(self, rid, n_nodes, full=False):
+        """Collect a finished request: (rho_molar, steps, residual, status), or
+        with full=True a dict that adds u, p and latency_s."""
         rho = np.zeros((self.p.ncomp, n_nodes))
+        u = np.zeros((self.p.D, n_nodes)) if full else None
+        pr = np.zeros(n_nodes) if full else None
         steps = C.c_long(0)
         res = C.c_double(0.0)
         status = C.c_int(0)
-        self._check(self.lib.fl_server_result(self.h, C.c_uint64(rid), _dp(rho), C.byref(steps), C.byref(res),
-                                              C.byref(status)), "fl_server_result")
+        lat = C.c_double(0.0)
+        self._check(self.lib.fl_server_result(self.h, C.c_uint64(rid), _dp(rho), _dp(u), _dp(pr), C.byref(steps),
+                                              C.byref(res), C.byref(status), C.byref(lat)), "fl_server_result")
+        if full:
+            return {"rho_molar": rho, "u": u, "p": pr, "steps": steps.value, "residual": res.value,
+                    "status": status.value, "latency_s": lat.value}
         return rho, steps.value, res.value, status.value
 
     def info(self):

@@ -86,26 +86,31 @@ def serve(server: F.Server, reqs, arrivals, tol, check_every, max_steps, tick_ms
         for rid in server.poll():
             i = inflight.pop(rid)
             r = reqs[i]
-            rho, steps, res, status = server.result(rid, r["L"] * r["ny"])
+            out = server.result(rid, r["L"] * r["ny"], full=True)
             t = time.perf_counter() - t0
-            rec = {"i": i, "L": r["L"], "steps": steps, "residual": res, "status": status,
-                   "arrival": float(arrivals[i]), "admitted": admitted[i], "done": t,
-                   "latency": t - float(arrivals[i])}
+            rec = {"i": i, "L": r["L"], "steps": out["steps"], "residual": out["residual"],
+                   "status": out["status"], "arrival": float(arrivals[i]), "admitted": admitted[i], "done": t,
+                   "latency": t - float(arrivals[i]), "service_s": out["latency_s"]}
             done.append(rec)
             if on_result:
-                on_result(rec, rho)
+                on_result(rec, out["rho_molar"])
         if time_limit_s and time.perf_counter() - t0 > time_limit_s:
             break
     wall = time.perf_counter() - t0
-    lat = [d["latency"] for d in done]
+    conv = [d for d in done if d["status"] == F.FL_OK]
+    lat = [d["latency"] for d in conv]
     span = (max(d["done"] for d in done) - min(d["arrival"] for d in done)) if done else float("nan")
     return {
         "requests": len(reqs), "completed": len(done),
-        "converged": sum(d["status"] == F.FL_OK for d in done),
+        "converged": len(conv),
         "max_steps_reached": sum(d["status"] == F.FL_ENOTCONV for d in done),
         "numeric_failures": sum(d["status"] == F.FL_ENUMERIC for d in done),
-        "solves_per_s": len(done) / span if done else 0.0,
-        "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
+        # throughput and latency count converged requests only (arrival to the
+        # result of a request whose residual fell below tol); requests stopped at
+        # max_steps or by a numeric failure are reported above, not counted here
+        "converged_solves_per_s": len(conv) / span if conv else 0.0,
+        "p50_time_to_equilibrium_s": percentile(lat, 50), "p99_time_to_equilibrium_s": percentile(lat, 99),
+        "largest_converged_L": max((d["L"] for d in conv), default=None),
         "wall_s": wall, "ticks": ticks, "admission_waits": rejected_admissions,
         "records": done,
     }

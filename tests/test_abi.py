@@ -65,6 +65,10 @@ def test_validate_accepts_workloads(lib):
     lambda p: (setattr(p.c, "force_model", 1), setattr(p.c, "precision", 1)),  # standard form: FP64 only
     lambda p: (setattr(p.c, "lattice", 1), setattr(p.c, "nx", 1024), setattr(p.c, "ny", 1024),
                setattr(p.c, "nz", 512)),                                     # 2^29 nodes
+    # D3Q19 576^3 binary FP64: populations of one direction fit 32-bit offsets
+    # (3.1e9 B), the force history of 3 doubles per node does not (4.6e9 B)
+    lambda p: (setattr(p.c, "lattice", 1), setattr(p.c, "nx", 576), setattr(p.c, "ny", 576),
+               setattr(p.c, "nz", 576)),
     lambda p: setattr(p._comp[0], "Tc", -1.0),
     lambda p: setattr(p._comp[1], "M", 0.0),
     lambda p: setattr(p._comp[0], "kappa", -0.1),
@@ -134,3 +138,15 @@ def test_sampled_timing_rejects_without_a_gpu_call(lib):
     k = C.c_int(8)
     t = C.c_long(0)
     assert lib.fl_step_timed_every(None, 10, 4, ms, None, C.byref(k), C.byref(t)) == F.FL_EINVAL
+
+
+def test_validate_accepts_largest_force_history_in_range(lib):
+    """D3Q19 binary FP64 at 520^3: N * 3 * 8 B = 3.37e9 B of force history, below 2^32."""
+    p = _params()
+    p.c.lattice, p.c.nx, p.c.ny, p.c.nz = 1, 520, 520, 520
+    assert p.validate() == F.FL_OK
+
+
+def test_tuning_calls_reject_null_handles(lib):
+    assert lib.fl_set_tuning(None, b"bands=8") == F.FL_EINVAL
+    assert lib.fl_server_set_tuning(None, b"serve=256") == F.FL_EINVAL

@@ -6,8 +6,6 @@ mistake) changes bits: the comparison is bitwise.  Shapes cover ragged
 256-node tiles, planes that do not split evenly over the 8 XCDs, FP64 and
 FP32 populations, BGK and MRT, and the full benchmark sizes.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -24,15 +22,8 @@ def announce(msg):
 
 
 def solver(w, precision, fused):
-    old = os.environ.get("FUGLBM_TUNE")
-    os.environ["FUGLBM_TUNE"] = "fused=1" if fused else "fused=0"
-    try:
-        s = F.Solver(F.Params.from_workload(w, precision=precision))
-    finally:
-        if old is None:
-            del os.environ["FUGLBM_TUNE"]
-        else:
-            os.environ["FUGLBM_TUNE"] = old
+    s = F.Solver(F.Params.from_workload(w, precision=precision))
+    s.set_tuning("fused=1" if fused else "fused=0")
     return s
 
 

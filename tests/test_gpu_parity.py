@@ -122,7 +122,7 @@ def test_isotropic_stencils_sphere_vs_oracle(coll):
     the EOS domain) on a D3Q19 sphere of the benchmark's binary mixture:
     FP64 element by element against the oracle's isotropic form, on a box
     that is not a multiple of the z-marching tile in x (so the plain kernel
-    runs either way); the z-marching form is never chosen for them."""
+    and the Laplacian pass run)."""
     shape = (26, 24, 20)
     w = wl.WORKLOADS["binary_slab_3d"].scaled(shape)
     w.collision = coll
@@ -133,15 +133,14 @@ def test_isotropic_stencils_sphere_vs_oracle(coll):
         o.run(k)
         s.step(k)
         compare(o, s, w, FP64_BAR, f"iso 3d {coll}")
-    # a 64 x 4-divisible box would take the z-marching form with the axis
-    # stencils; with the isotropic ones the plain kernel runs
+    # a box whose x extent is a multiple of 64 and y of 4 takes the z-marching
+    # form, which computes -lap(phi) itself (no Laplacian pass)
     w2 = wl.WORKLOADS["binary_slab_3d"].scaled((64, 8, 8))
     p = F.Params.from_workload(w2, precision="fp32", stencil="isotropic")
     s2 = F.Solver(p)
     s2.set_state(*wl.initial_field(w2))
     names = s2.step_timed(2)
-    assert any("collide_stream" in k for k in names) and not any("zmarch" in k for k in names), names
-    assert "k_interface_lap" in names, names
+    assert list(names) == ["k_moments_eos", "k_collide_zmarch_iso"], names
 
 
 def test_isotropic_stencils_2d_and_fp32():

@@ -33,8 +33,9 @@ def some_requests(n, seed=0):
     return reqs
 
 
-def run_server(p, reqs, tol, check, max_steps, tick, pool=1 << 28, order=None):
+def run_server(p, reqs, tol, check, max_steps, tick, pool=1 << 28, order=None, tune=None):
     srv = F.Server(p, pool_bytes=pool, max_slots=64)
+    srv.set_tuning(tune)
     ids = {}
     for i in (order if order is not None else range(len(reqs))):
         r = reqs[i]
@@ -172,21 +173,12 @@ def test_request_cap_per_tick_bitwise():
     """Advancing at most two requests per tick (oldest first; the rest wait
     admitted) gives every request the same result, bit for bit, as advancing
     all of them, and every request completes."""
-    import os
-
     announce("request cap per tick")
     reqs = some_requests(5, seed=7)
-    old = os.environ.get("FUGLBM_TUNE")
-    try:
-        os.environ["FUGLBM_TUNE"] = "serve_cap=2"
-        capped = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300)
-        os.environ["FUGLBM_TUNE"] = "serve_cap=0"
-        free = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300)
-    finally:
-        if old is None:
-            os.environ.pop("FUGLBM_TUNE", None)
-        else:
-            os.environ["FUGLBM_TUNE"] = old
+    capped = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300,
+                        tune="serve_cap=2")
+    free = run_server(base_params("fp32"), reqs, tol=1e-9, check=200, max_steps=2000, tick=300,
+                      tune="serve_cap=0")
     assert sorted(capped) == sorted(free) == list(range(len(reqs)))
     for i in range(len(reqs)):
         a, b = capped[i], free[i]

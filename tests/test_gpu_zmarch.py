@@ -8,8 +8,6 @@ slot, halo offset or register shift changes bits.  Shapes cover several
 tiles in x and y, z-ranges that do not divide nz, a single plane, FP64 and
 FP32 populations, BGK and MRT, and the two benchmark lattices.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -26,15 +24,8 @@ def announce(msg):
 
 
 def solver(w, precision, tune):
-    old = os.environ.get("FUGLBM_TUNE")
-    os.environ["FUGLBM_TUNE"] = tune
-    try:
-        s = F.Solver(F.Params.from_workload(w, precision=precision))
-    finally:
-        if old is None:
-            del os.environ["FUGLBM_TUNE"]
-        else:
-            os.environ["FUGLBM_TUNE"] = old
+    s = F.Solver(F.Params.from_workload(w, precision=precision))
+    s.set_tuning(tune)
     return s
 
 
@@ -145,3 +136,92 @@ def test_sweep_order_bitwise(wname, shape, precision, coll):
         if ref is None:
             ref = g
         assert np.array_equal(g, ref), tune
+
+
+def _sphere(w, shape, R):
+    rL, rV, _ = w.phase_densities()
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2)
+    ind = 0.5 * (1 - np.tanh((r - R) / 2.0))
+    return np.stack([rV[i] + (rL[i] - rV[i]) * ind for i in range(len(rL))])
+
+
+ISO_CASES = [
+    # workload, shape, precision, collision, zlen
+    ("ternary_droplets_3d", (64, 12, 16), "fp32", "MRT", 16),
+    ("ternary_droplets_3d", (128, 8, 11), "fp32", "MRT", 4),   # ragged last z-range, two tiles in x
+    ("ternary_droplets_3d", (64, 8, 7), "fp64", "MRT", 3),
+    ("binary_slab_3d", (64, 8, 9), "fp32", "BGK", 2),
+    ("binary_slab_3d", (64, 4, 1), "fp64", "BGK", 16),         # one plane: z -+ 1 wrap onto itself
+    ("binary_slab_3d", (64, 4, 2), "fp32", "MRT", 1),          # two planes, one per workgroup
+]
+
+
+@pytest.mark.parametrize("wname,shape,precision,coll,zlen", ISO_CASES)
+def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zlen):
+    """The z-marching kernel with the isotropic stencils (which forms
+    -lap(phi) and mu_i in LDS as planes pass) against the one-thread-per-node
+    kernel after the Laplacian pass: the same per-node expressions, so the
+    same bits, on a droplet that varies along every axis."""
+    w = wl.WORKLOADS[wname].scaled(shape)
+    w.collision = coll
+    announce(f"iso zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen}")
+    rho = _sphere(w, shape, 0.3 * min(shape[:2]) if shape[2] > 2 else 1.5)
+    p = F.Params.from_workload(w, precision=precision, stencil="isotropic")
+    a, b = F.Solver(p), F.Solver(p)
+    a.set_tuning(f"zmarch=1,zlen={zlen}")
+    b.set_tuning("zmarch=0")
+    a.set_state(rho)
+    b.set_state(rho)
+    assert list(a.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch_iso"]
+    assert set(b.step_timed(1)) == {"k_moments_eos", "k_collide_stream", "k_interface_lap"}
+    a.step(14)
+    b.step(14)
+    ga, gb = a.populations(), b.populations()
+    print(f"  max |diff| {np.max(np.abs(ga - gb)):.3e}", flush=True)
+    assert np.array_equal(ga, gb)
+    assert np.array_equal(a.fields()["u"], b.fields()["u"])
+    a.close()
+    b.close()
+
+
+def test_zmarch_isotropic_fp64_vs_oracle():
+    """FP64 z-marching isotropic kernel against the oracle's isotropic form on
+    a ternary sphere (MRT), element by element (1e-12)."""
+    shape = (64, 12, 10)
+    w = wl.WORKLOADS["ternary_droplets_3d"].scaled(shape)
+    announce(f"iso zmarch FP64 vs oracle {shape}")
+    rho = _sphere(w, shape, 4.0).reshape(3, -1)
+    o = oracle_for(w, stencil="isotropic")
+    o.init(rho)
+    s = F.Solver(F.Params.from_workload(w, precision="fp64", stencil="isotropic"))
+    s.set_state(rho)
+    assert list(s.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch_iso"]
+    o.run(1)
+    s.step(29)
+    o.run(29)
+    e, _ = F.lattice_table(w.lattice)
+    err = rel(s.populations(), o.g[:, direction_map(w.lattice, e), :])
+    er = rel(s.fields()["rho_molar"], o.fields()["rho_molar"])
+    print(f"  pops {err:.2e} rho {er:.2e}", flush=True)
+    assert err < 1e-12 and er < 1e-12
+
+
+def test_bench_lattice_isotropic_zmarch_equals_plain():
+    """The 256^3 ternary two-droplet lattice of the benchmark (FP32, MRT,
+    isotropic stencils): z-marching and one-thread-per-node kernels bitwise
+    equal after three steps."""
+    w = wl.WORKLOADS["ternary_droplets_3d"]
+    announce(f"bench lattice isotropic {w.shape}")
+    rho, u = wl.initial_field(w)
+    out = []
+    for tune in ("zmarch=1", "zmarch=0"):
+        s = F.Solver(F.Params.from_workload(w, precision="fp32", stencil="isotropic"))
+        s.set_tuning(tune)
+        s.set_state(rho, u)
+        s.step(3)
+        out.append(s.fields()["rho_molar"])
+        s.close()
+        del s
+    assert np.array_equal(out[0], out[1])

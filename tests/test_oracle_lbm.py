@@ -502,3 +502,40 @@ def test_3d_sphere_needs_isotropic_stencils():
     f = b.fields()
     assert np.abs(f["u"]).max() < 0.05
     assert np.max(np.abs(b.mass() - m0) / m0) < 1e-12
+
+
+@pytest.mark.parametrize("name,shape", [("D2Q9", (17, 13)), ("D3Q19", (15, 13, 11))])
+def test_isotropic_stencils_exact_on_quadratic_fields(name, shape):
+    """On any quadratic field f = c + b.r + r.H r / 2 the isotropic stencils
+    are exact: sum_a w_a e_a = 0, sum_a w_a e_a e_a = c_s^2 I and the odd third
+    moment vanish, so grad f = b + H r and lap f = tr H at every node whose
+    stencil does not cross the periodic wrap.  H is genuinely 3-D (every
+    off-diagonal entry non-zero), so a wrong weight, velocity or sign in any
+    direction -- diagonal ones included -- breaks one of the identities."""
+    w = wl.WORKLOADS["binary_slab_2d"]
+    o = lbm.OracleLBM(mixture_of(w), name, shape)
+    D = o.D
+    rng = np.random.Generator(np.random.PCG64(11))
+    A = rng.uniform(-1.0, 1.0, (D, D))
+    H = A + A.T
+    b = rng.uniform(-1.0, 1.0, D)
+    c = 0.7
+    nz = shape[2] if D == 3 else 1
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(shape[1]), np.arange(shape[0]), indexing="ij")
+    r = np.stack([x, y, z][:D]).reshape(D, -1).astype(np.float64)
+    r -= np.array([s / 2.0 for s in shape[:D]])[:, None]
+    f = c + b @ r + 0.5 * np.einsum("in,ij,jn->n", r, H, r)
+    grad, lap = o.iso_stencils(f)
+    inner = np.ones(r.shape[1], dtype=bool)
+    for k, (xk, nk) in enumerate(zip([x, y, z][:D], shape[:D])):
+        xk = xk.reshape(-1)
+        inner &= (xk >= 1) & (xk <= nk - 2)
+    exact_grad = b[:, None] + H @ r
+    scale = np.max(np.abs(f))
+    assert inner.sum() > 0.5 * inner.size
+    assert np.max(np.abs(grad[:, inner] - exact_grad[:, inner])) < 1e-13 * scale
+    assert np.max(np.abs(lap[inner] - np.trace(H))) < 1e-13 * scale
+    # a linear field has zero Laplacian everywhere inside, and the gradient b
+    g1, l1 = o.iso_stencils(c + b @ r)
+    assert np.max(np.abs(g1[:, inner] - b[:, None])) < 1e-13 * scale
+    assert np.max(np.abs(l1[inner])) < 1e-13 * scale

@@ -39,7 +39,10 @@ class StandInServer:
             del self.live[rid]
         return out
 
-    def result(self, rid, n):
+    def result(self, rid, n, full=False):
+        if full:
+            return {"rho_molar": np.zeros(n), "u": np.zeros(n), "p": np.zeros(n), "steps": 100,
+                    "residual": 0.0, "status": F.FL_OK, "latency_s": 0.0}
         return np.zeros(n), 100, 0.0, F.FL_OK
 
 
@@ -51,7 +54,8 @@ def reqs():
 def test_largest_first_admits_longest_lattices_first(reqs):
     srv = StandInServer(slots=4)
     out = serving.serve(srv, reqs, np.zeros(len(reqs)), 1e-10, 1000, 50000, policy="largest_first")
-    assert out["completed"] == len(reqs)
+    assert out["completed"] == out["converged"] == len(reqs)
+    assert out["converged_solves_per_s"] > 0 and out["p99_time_to_equilibrium_s"] >= 0
     assert srv.admitted == sorted((r["L"] for r in reqs), reverse=True)
 
 
@@ -74,3 +78,24 @@ def test_largest_first_never_admits_before_arrival(reqs):
     assert srv.admitted[-1] == reqs[big]["L"]
     rest = [r["L"] for k, r in enumerate(reqs) if k != big]
     assert srv.admitted[:-1] == sorted(rest, reverse=True)
+
+
+def test_metrics_count_converged_requests_only(reqs):
+    """Requests stopped at max_steps or by a numeric failure are reported but
+    enter neither the throughput nor the time-to-equilibrium percentiles."""
+
+    class Mixed(StandInServer):
+        def result(self, rid, n, full=False):
+            st = (F.FL_OK, F.FL_ENOTCONV, F.FL_ENUMERIC)[rid % 3]
+            return {"rho_molar": np.zeros(n), "u": np.zeros(n), "p": np.zeros(n), "steps": 100,
+                    "residual": 0.0, "status": st, "latency_s": 0.0}
+
+    srv = Mixed(slots=64)
+    out = serving.serve(srv, reqs, np.zeros(len(reqs)), 1e-10, 1000, 50000)
+    conv = [r for r in out["records"] if r["status"] == F.FL_OK]
+    assert out["completed"] == len(reqs)
+    assert out["converged"] == len(conv) == len(reqs) // 3
+    assert out["max_steps_reached"] == out["numeric_failures"] == len(reqs) // 3
+    span = max(r["done"] for r in out["records"]) - min(r["arrival"] for r in out["records"])
+    assert abs(out["converged_solves_per_s"] - len(conv) / span) < 1e-9 * out["converged_solves_per_s"]
+    assert out["p99_time_to_equilibrium_s"] <= max(r["latency"] for r in conv) + 1e-12

@@ -62,3 +62,50 @@ def test_slab_order_is_y_major_inside_a_slab():
     assert rows[:6] == [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1)]
     assert rows[-3:] == [(0, 4), (1, 4), (2, 4)]
     assert np.array_equal(x[:nx], np.arange(nx))
+
+
+def band_node(b, t, bs, nx, ny, nz, bands, rev):
+    """The kernels' XCD-band order: XCD b % 8 sweeps its row bands along z."""
+    k, j = b & 7, b >> 3
+    maxrows = (ny + bands - 1) // bands
+    bpp = (maxrows * nx + bs - 1) // bs
+    m = j // (bpp * nz)
+    r = j - m * bpp * nz
+    z = r // bpp
+    q = k + 8 * m
+    Y0, Y1 = q * ny // bands, (q + 1) * ny // bands
+    pos = (r - z * bpp) * bs + t
+    if rev:
+        z = nz - 1 - z
+    n = pos % nx + nx * (Y0 + pos // nx + ny * z)
+    return np.where((m >= bands // 8) | (pos >= (Y1 - Y0) * nx), -1, n)
+
+
+@pytest.mark.parametrize("shape", [(256, 64, 12), (64, 12, 17), (48, 9, 5), (200, 3, 2), (16, 16, 9), (40, 33, 3)])
+@pytest.mark.parametrize("bs", [64, 256])
+@pytest.mark.parametrize("bands", [8, 16, 32])
+@pytest.mark.parametrize("rev", [False, True])
+def test_band_order_is_a_bijection(shape, bs, bands, rev):
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    maxrows = (ny + bands - 1) // bands
+    grid = bands * ((maxrows * nx + bs - 1) // bs) * nz
+    b = np.repeat(np.arange(grid), bs)
+    t = np.tile(np.arange(bs), grid)
+    n = band_node(b, t, bs, nx, ny, nz, bands, rev)
+    seen = n[n >= 0]
+    assert seen.size == N
+    assert np.array_equal(np.sort(seen), np.arange(N))
+
+
+def test_band_order_sweeps_z_inside_a_band():
+    """XCD 0's blocks visit band 0's rows plane by plane before its next band."""
+    nx, ny, nz, bands, bs = 8, 32, 3, 16, 8
+    maxrows = ny // bands
+    bpp = maxrows * nx // bs
+    b = np.arange(0, 8 * 2 * bpp * nz, 8)          # XCD 0's blocks in dispatch order
+    n = np.array([band_node(bb, 0, bs, nx, ny, nz, bands, False) for bb in b])
+    y, z = (n // nx) % ny, n // (nx * ny)
+    assert list(z[:2 * nz]) == [0, 0, 1, 1, 2, 2]
+    assert set(y[:2 * nz]) == {0, 1}
+    assert set(y[2 * nz:]) == {16, 17}                # band 8 = XCD 0's second band
