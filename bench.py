@@ -19,9 +19,11 @@ timed on the host cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,7 +51,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(w, precision, stencil="axis"):
+def algorithmic_bytes(w, precision, stencil="axis", lap_pass=None):
     """Algorithmic HBM bytes per node of each kernel of one step.
 
     k_moments_eos: read every population, write rho~_i, ln f_i and phi (FP64).
@@ -58,7 +60,10 @@ def algorithmic_bytes(w, precision, stencil="axis"):
     ln f_i and phi (axis stencils) or -lap(phi) (isotropic stencils) once (the
     stencil re-reads are cache traffic), read and write the previous force sum
     (D values).  The FP32 form also reads the rest-population reference.
-    k_interface_lap (isotropic stencils only): read phi, write -lap(phi).
+    k_interface_lap (isotropic stencils, when the collide pass is the
+    one-thread-per-node kernel): read phi, write -lap(phi).
+    k_collide_zmarch_iso (isotropic stencils, z-marching): reads phi instead of
+    -lap(phi), which it forms itself; no Laplacian pass then runs.
     k_fused_step: the whole step, i.e. the per-node-step figure.
     """
     Q = 9 if w.lattice == "D2Q9" else 19
@@ -70,14 +75,16 @@ def algorithmic_bytes(w, precision, stencil="axis"):
     aux = 8 * (2 * nc + 1)          # rho~_i, ln f_i and phi or -lap(phi) (FP64)
     k1 = pops + ref + aux
     k2 = 2 * pops + ref + aux + 2 * s * D
-    lap = 16 if stencil == "isotropic" else 0
+    if lap_pass is None:
+        lap_pass = stencil == "isotropic"
+    lap = 16 if lap_pass else 0
     # per-node-step figure: populations once in and out, the FP64 densities,
     # ln f and the interface field once each way, the force history (population
     # precision) once each way, the FP32 form's rest-population reference once,
     # and with the isotropic stencils the Laplacian pass (phi in, -lap(phi) out)
     step = 2 * pops + 2 * aux + 2 * s * D + ref + lap
-    out = {"k_moments_eos": k1, "k_collide_stream": k2, "k_collide_zmarch": k2, "k_fused_step": step,
-           "step": step}
+    out = {"k_moments_eos": k1, "k_collide_stream": k2, "k_collide_zmarch": k2, "k_collide_zmarch_iso": k2,
+           "k_fused_step": step, "step": step}
     if lap:
         out["k_interface_lap"] = lap
     return out
@@ -268,6 +275,76 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, pl
     }
 
 
+def _kernel_short(name):
+    """'void fl::k_collide_stream<1, 3, float, true, true>(...)' -> 'k_collide_stream'."""
+    m = re.search(r"fl::(k_[a-z0-9_]+)", name)
+    return m.group(1) if m else name.split("(")[0]
+
+
+def _pmc_per_dispatch(csv_path):
+    """{kernel name: [counter value per dispatch]} of a rocprofv3 --pmc CSV
+    (one counter; rows repeated for one dispatch are counted once)."""
+    seen, out = set(), {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            key = (row["Dispatch_Id"], row["Counter_Name"])
+            if key in seen:
+                continue
+            seen.add(key)
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def write_traffic(fetch_csv, write_csv, w, stencil, copy_bytes=1 << 30):
+    """HBM bytes per launch of each kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+    `bench.py --copy-calibration`: each counter is scaled by what it reads for
+    the 1 GiB device copy in the same run (copy_bytes read and written).
+    Writes profiles/traffic.json and prints a markdown table."""
+    fetch, write = _pmc_per_dispatch(fetch_csv), _pmc_per_dispatch(write_csv)
+
+    def scale(d):
+        vals = [v for k, vs in d.items() if "copyBuffer" in k or "copy" in k.lower() for v in vs
+                if v * 1024 > 0.25 * copy_bytes]
+        if not vals:
+            raise SystemExit("no 1 GiB copy dispatch in the counter file (run with --copy-calibration)")
+        return copy_bytes / (1024.0 * float(np.mean(vals)))
+
+    sf, sw = scale(fetch), scale(write)
+    rows = []
+    for name in sorted(set(fetch) & set(write)):
+        if "fl::" not in name:
+            continue
+        r = float(np.mean(fetch[name])) * 1024 * sf
+        wbytes = float(np.mean(write[name])) * 1024 * sw
+        rows.append({"kernel": _kernel_short(name), "template": name.split("(")[0].replace("void ", ""),
+                     "workload": w.name, "nodes": w.nodes, "stencil": stencil, "launches": len(fetch[name]),
+                     "read_bytes": round(r), "write_bytes": round(wbytes), "bytes_per_launch": round(r + wbytes),
+                     "bytes_per_node": round((r + wbytes) / w.nodes, 1)})
+    out = {"kernel_source_hash": kernel_source_hash(), "date": time.strftime("%Y-%m-%d"),
+           "scale": {"FETCH_SIZE": sf, "WRITE_SIZE": sw}, "kernels": rows}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"Scale factors from a {copy_bytes >> 20} MiB device copy: FETCH_SIZE x{sf:.4f}, WRITE_SIZE x{sw:.4f}.\n")
+    print("| kernel | launches | scaled read MB | scaled write MB | bytes/node |")
+    print("|---|---|---|---|---|")
+    for r in rows:
+        print(f"| `{r['template']}` | {r['launches']} | {r['read_bytes'] / 1e6:.1f} | {r['write_bytes'] / 1e6:.1f} | "
+              f"{r['bytes_per_node']} |")
+
+
+def trace_summary(stats_csv):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    print("| kernel | calls | avg us | min us | max us | % time |")
+    print("|---|---|---|---|---|---|")
+    with open(stats_csv) as f:
+        for row in csv.DictReader(f):
+            name = row["Name"].split("(")[0].replace("void ", "")
+            print(f"| `{name}` | {row['Calls']} | {float(row['AverageNs']) / 1e3:.1f} | "
+                  f"{float(row['MinNs']) / 1e3:.1f} | {float(row['MaxNs']) / 1e3:.1f} | "
+                  f"{float(row['Percentage']):.2f} |")
+
+
 def default_stencil(w):
     """The isotropic stencils for droplets in 3-D (the axis ones leave the EOS
     domain there within tens of steps), the paper's axis stencils otherwise."""
@@ -305,7 +382,7 @@ def measure_lattice(w, precision, stencil, state, steps, warmup, tuning=None):
     print(f"[bench] timed {steps} steps in {wall:.3f} s ({timed_launches} of them with events)",
           file=sys.stderr, flush=True)
     nodes = w.nodes
-    ab = algorithmic_bytes(w, precision, stencil)
+    ab = algorithmic_bytes(w, precision, stencil, lap_pass="k_interface_lap" in kavg)
     dominant = max(kavg, key=kavg.get)
     avg_ms = kavg[dominant]
     achieved = ab[dominant] * nodes / (avg_ms * 1e-3) / 1e9
@@ -370,7 +447,20 @@ def main():
                     help="print the attainable HBM rates of the kernels' access patterns and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (PMC byte-counter scale)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files of a "
+                         "--copy-calibration run (no GPU needed) and exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown table of a rocprofv3 --stats kernel_stats.csv and exit")
     args = ap.parse_args()
+
+    if args.traffic_from or args.trace_summary:
+        w = wl.WORKLOADS[args.workload]
+        if args.traffic_from:
+            write_traffic(*args.traffic_from, w, args.stencil or default_stencil(w))
+        else:
+            trace_summary(args.trace_summary)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU (how the lattice would be cut into z-slabs "

@@ -875,9 +875,15 @@ __global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(K
 // result is the same bit for bit.  Per node plane z, two barriers: after the
 // stencil reads (plane z-1's buffer is then refilled with plane z+2, and the
 // phi slot of plane z with plane z+4), and at the end.  Planes z0-1 .. z1 of
-// mu_i and rho~_i and z0-2 .. z1+1 of phi pass through a workgroup.
+// mu_i and rho~_i and z0-2 .. z1+1 of phi pass through a workgroup.  With
+// two or three components the collision alone needs nearly all of 256
+// registers, so the kernel runs at one wave per SIMD there (at two, 150
+// registers spilled to scratch memory and the pass took 3.4 times as long on
+// the 256^3 ternary lattice); a fourth plane buffer removing the first
+// barrier, with the next plane's node inputs loaded across the second,
+// measured slower (2.72 against 2.60 ms).
 template <int NC, typename P>
-constexpr int kZmarchIsoWaves = sizeof(P) == 4 ? 2 : 1;
+constexpr int kZmarchIsoWaves = (sizeof(P) == 4 && NC == 1) ? 2 : 1;
 
 __device__ __forceinline__ int mod3(int q) { return ((q % 3) + 3) % 3; }
 
