@@ -303,6 +303,21 @@ int fl_server_poll(fl_server* srv, uint64_t* ids, int cap, int* n);
 int fl_server_result(fl_server* srv, uint64_t id, double* rho_molar, double* u, double* p, long* steps,
                      double* residual, int* status, double* latency_s);
 
+/* fl_server_result for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same outputs, computed by the same kernel, but the velocity and pressure
+ * are staged in a static device array of 2^18 doubles (2 MiB), which every GPU
+ * the library runs on holds until the process ends, instead of in memory
+ * allocated per call.  Makes no hipMalloc, hipFree or other allocating call.
+ * A request needing more than 2^18 doubles of staging, (D + 1) * N, i.e. more
+ * than 87 381 D2Q9 or 65 536 D3Q19 nodes, is refused with FL_EINVAL and stays
+ * collectable with fl_server_result.  Calls on one GPU share the array:
+ * calls that overlap in time (servers on different streams or host threads)
+ * race, and the caller must serialise them.  No element needs to start at
+ * zero: a call writes every element it reads. */
+int fl_server_result_noalloc(fl_server* srv, uint64_t id, double* rho_molar, double* u, double* p,
+                             long* steps, double* residual, int* status, double* latency_s);
+
 /* Occupancy: requests in flight, free slots, pool bytes in use and total. */
 int fl_server_info(const fl_server* srv, int* active, int* free_slots, size_t* pool_used,
                    size_t* pool_total);

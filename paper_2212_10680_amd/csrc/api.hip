@@ -860,6 +860,39 @@ int fl_set_state_raw(fl_solver* s, const void* host_buf, size_t bytes) {
 
 // ===================================================================== server
 #include <chrono>
+#include <mutex>
+
+namespace {
+
+// Device staging of fl_server_result_noalloc: the velocity and pressure of one
+// finished request, (D + 1) N doubles (2 MiB: requests of up to 87 381 D2Q9 or
+// 65 536 D3Q19 nodes).  Every GPU the library runs on holds its own copy until
+// the process ends.  Host code never uses the array's name as an address: it
+// uses the pointer hipGetSymbolAddress returns for the current device.
+constexpr size_t kResultScratchDoubles = size_t(1) << 18;
+static __device__ __align__(256) double scratch[kResultScratchDoubles];
+
+// This device's address of scratch, resolved once per device (with that
+// device current) and kept.
+hipError_t resolve_result_scratch(double** out) {
+    static std::mutex mu;
+    static double* per_device[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!per_device[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        per_device[dev] = static_cast<double*>(ptr);
+    }
+    *out = per_device[dev];
+    return hipSuccess;
+}
+
+}  // namespace
 
 
 namespace {
@@ -877,6 +910,8 @@ struct fl_server {
     // creation (max_slots + 2) is never exceeded and retiring a request
     // allocates no host memory either
     std::vector<std::pair<size_t, size_t>> free_list;
+    double* result_scratch = nullptr;    // this device's static result staging (fl_server_result_noalloc)
+    std::string scratch_error;
     int max_slots = 0;
     struct Req {
         uint64_t id;
@@ -1004,6 +1039,13 @@ int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, vo
     }
     s->free_list.reserve((size_t)max_slots + 2);
     s->free_list.push_back({0, s->pool_bytes});
+    // this device's result staging of fl_server_result_noalloc, resolved once
+    // per device; a failure here only disables that entry point
+    if (resolve_result_scratch(&s->result_scratch) != hipSuccess) {
+        s->result_scratch = nullptr;
+        s->scratch_error = "static result scratch: hipGetSymbolAddress failed";
+        (void)hipGetLastError();
+    }
     *out = s;
     return FL_OK;
 }
@@ -1219,6 +1261,27 @@ int fl_server_result(fl_server* s, uint64_t id, double* rho_molar, double* u, do
         SRV_TRY(s, hipMallocAsync((void**)&tmp, sizeof(double) * (s->cfg.D + 1) * (size_t)r.d.N, s->cfg.stream));
         const int rc = server_fields(s, r, tmp, rho_molar, u, p);
         (void)hipFreeAsync(tmp, s->cfg.stream);
+        if (rc != FL_OK) return rc;
+    }
+    retire_request(s, k, steps, residual, status, latency_s);
+    return FL_OK;
+}
+
+int fl_server_result_noalloc(fl_server* s, uint64_t id, double* rho_molar, double* u, double* p, long* steps,
+                             double* residual, int* status, double* latency_s) {
+    if (!s) return FL_EINVAL;
+    const int k = find_request(s, id);
+    if (k < 0) return sfail(s, FL_EINVAL, "unknown request id");
+    const fl_server::Req& r = s->reqs[k];
+    if (r.d.status == fl::kSlotRunning) return FL_EAGAIN;
+    if (rho_molar || u || p) {
+        const size_t need = (size_t)(s->cfg.D + 1) * (size_t)r.d.N;
+        if (need > kResultScratchDoubles)
+            return sfail(s, FL_EINVAL, "request of " + std::to_string(r.d.N) + " nodes needs " + std::to_string(need) +
+                                           " doubles of result staging, more than the static " +
+                                           std::to_string(kResultScratchDoubles) + ": use fl_server_result");
+        if (!s->result_scratch) return sfail(s, FL_EDEVICE, s->scratch_error);
+        const int rc = server_fields(s, r, s->result_scratch, rho_molar, u, p);
         if (rc != FL_OK) return rc;
     }
     retire_request(s, k, steps, residual, status, latency_s);

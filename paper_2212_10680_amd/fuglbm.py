@@ -86,6 +86,8 @@ SIGNATURES = {
     "fl_server_poll": (C.c_int, [_VP, C.POINTER(C.c_uint64), C.c_int, C.POINTER(C.c_int)]),
     "fl_server_result": (C.c_int, [_VP, C.c_uint64, _DP, _DP, _DP, C.POINTER(C.c_long), _DP, C.POINTER(C.c_int),
                                    _DP]),
+    "fl_server_result_noalloc": (C.c_int, [_VP, C.c_uint64, _DP, _DP, _DP, C.POINTER(C.c_long), _DP,
+                                           C.POINTER(C.c_int), _DP]),
     "fl_server_info": (C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
                                  C.POINTER(C.c_size_t)]),
 }
