@@ -133,3 +133,24 @@ def damped_period(t, r, guess):
     p, _ = curve_fit(f, t, r, p0=p0, maxfev=20000)
     return abs(p[3]), p
 
+
+
+def swing_statistics(rows, mix, z, names):
+    """Per error of eq. eqerror, over sampled rows of a state whose bulk values
+    move (the swinging slab of Sec. IV.C, R-26): (mean, std, min, max, window
+    shift).  The window shift is the mean difference between the errors from
+    the central-quarter bulk window (R-17) and from the two nodes nearest each
+    region's centre: the paper does not say where it takes its bulk values."""
+    samples = {}
+    for r in rows:
+        r = np.asarray(r)
+        e = flash_errors_percent(mix, z, *bulk_values(r), names=names)
+        ep = flash_errors_percent(mix, z, *central_pairs(r), names=names)
+        for phase in e:
+            for k in e[phase]:
+                samples.setdefault((phase, k), []).append((e[phase][k], ep[phase][k]))
+    out = {}
+    for key, v in samples.items():
+        v = np.array(v)
+        out[key] = (v[:, 0].mean(), v[:, 0].std(), v[:, 0].min(), v[:, 0].max(), abs((v[:, 1] - v[:, 0]).mean()))
+    return out

@@ -39,8 +39,8 @@ from oracle import fixed_point as fp
 from paper_2212_10680_amd import fuglbm as F
 from paper_2212_10680_amd import workloads as wl
 
-from _util import (bulk_values, central_pairs, damped_period, direction_map, flash_errors_percent,
-                   half_width, mixture_of, oracle_for, rel, smooth_3d_field)
+from _util import (bulk_values, damped_period, direction_map, flash_errors_percent,
+                   half_width, mixture_of, oracle_for, rel, smooth_3d_field, swing_statistics)
 
 pytestmark = pytest.mark.gpu
 
@@ -177,45 +177,52 @@ def test_paper_case_parity(wname, steps):
         compare(o, s, w, wname)
 
 
-def test_e5_reproduces_table_tabcase3():
-    """The paper's errors after 1e6 steps against the distribution of ours over
-    the 5e4 steps that follow (R-26): at 1e6 steps the liquid slab still swings
-    about a lattice-pinned position (period ~4e4 steps, |u| <= 3e-4) and the
-    bulk values move with its phase, so the printed numbers are one sample of
-    that swing.  Each must lie within 3 standard deviations of our mean, plus
-    the shift that the choice of the bulk window makes (R-17: the paper does not
-    say where it takes bulk values, and the 46-node liquid slab is not bulk at
-    its centre; measured as the mean difference between the central-quarter and
-    the central-pair averages), plus 0.005 percentage points."""
+E5_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "e5_golden.json")
+
+
+def test_e5_swing_matches_oracle():
+    """The paper's 1e6 steps and the 5e4 after them (100 samples every 500
+    steps) on the GPU, against the FP64 oracle's run of the same case
+    (tests/golden/e5_golden.json, written by write_e5_golden.py from oracle/
+    alone).  At 1e6 steps the liquid slab swings about a lattice-pinned position
+    (R-26) and the phase of that swing depends on rounding (the two runs agree
+    element by element over the first 1 000 steps, test_paper_case_parity, and
+    differ by a few percent pointwise at 1e6), so the runs are compared by the
+    statistics of the swing: per error of Table tabcase3, the means within half
+    a standard deviation plus 0.002 percentage points (a window of 1.25 periods
+    averages a phase-shifted swing to within about a third of its standard
+    deviation), the standard deviations within a quarter plus 0.001 points.
+    The oracle's swing is held against the paper's values on the CPU
+    (test_e5_oracle_swing_reproduces_table_tabcase3)."""
     w = wl.WORKLOADS["e5_c1c2c3"]
-    announce("E5: 1e6 steps, then 100 samples every 500 steps")
+    with open(E5_GOLDEN) as f:
+        gold = json.load(f)
+    nx, ny = w.shape
+    assert gold["shape"] == [nx, ny]
+    announce(f"E5: {gold['first']} steps, then {len(gold['rows'])} samples every {gold['every']} steps")
     rho, _ = wl.initial_field(w)
     s = F.Solver(F.Params.from_workload(w, precision="fp64"))
     s.set_state(rho)
-    s.step(1_000_000)
-    mix = mixture_of(w)
-    samples = {}
-    for i in range(100):
-        r = s.fields()["rho_molar"].reshape(3, 2, 200)
-        if i == 0:
-            assert np.array_equal(r[:, 0], r[:, 1])
-        rL, rV = bulk_values(r[:, 0])
-        errs = flash_errors_percent(mix, [0.4, 0.3, 0.3], rL, rV, names=("C1", "C2", "C3"))
-        pL, pV = central_pairs(r[:, 0])
-        errs_pair = flash_errors_percent(mix, [0.4, 0.3, 0.3], pL, pV, names=("C1", "C2", "C3"))
-        for phase, e in errs.items():
-            for k, v in e.items():
-                samples.setdefault((phase, k), []).append((v, errs_pair[phase][k]))
-        s.step(500)
+    s.step(gold["first"])
+    rows, worst = [], 0.0
+    for ref in gold["rows"]:
+        r = s.fields()["rho_molar"].reshape(3, ny, nx)
+        assert np.array_equal(r[:, 0], r[:, 1])
+        worst = max(worst, rel(r[:, 0], np.array(ref)))
+        rows.append(r[:, 0])
+        s.step(gold["every"])
     s.close()
-    for (phase, k), v in samples.items():
-        v = np.array(v)
-        mean, std = v[:, 0].mean(), v[:, 0].std()
-        window = abs((v[:, 1] - v[:, 0]).mean())
-        paper = TAB3[phase][k]
-        print(f"  {phase} {k}: paper {paper:.4f}, ours mean {mean:.4f} std {std:.4f} "
-              f"range [{v[:, 0].min():.4f}, {v[:, 0].max():.4f}], window shift {window:.4f}", flush=True)
-        assert abs(paper - mean) <= 3 * std + window + 0.005, (phase, k, paper, mean, std, window)
+    print(f"  largest pointwise difference from the oracle over the samples: {worst:.2e}", flush=True)
+    mix = mixture_of(w)
+    names = ("C1", "C2", "C3")
+    ours = swing_statistics(rows, mix, [0.4, 0.3, 0.3], names)
+    orc = swing_statistics(gold["rows"], mix, [0.4, 0.3, 0.3], names)
+    for key, (mean, std, lo, hi, window) in ours.items():
+        om, osd = orc[key][0], orc[key][1]
+        print(f"  {key[0]} {key[1]}: paper {TAB3[key[0]][key[1]]:.4f}; GPU mean {mean:.4f} std {std:.4f} "
+              f"range [{lo:.4f}, {hi:.4f}]; oracle mean {om:.4f} std {osd:.4f}", flush=True)
+        assert abs(mean - om) <= 0.5 * osd + 0.002, (key, mean, om, osd)
+        assert abs(std - osd) <= 0.25 * osd + 0.001, (key, std, osd)
 
 
 # ------------------------------------------------------------ Sec. IV.D, E6

@@ -26,7 +26,7 @@ from oracle import fixed_point as fp
 from oracle import thermo as th
 from paper_2212_10680_amd import workloads as wl
 
-from _util import bulk_values, central_pairs, flash_errors_percent, mixture_of
+from _util import bulk_values, central_pairs, flash_errors_percent, mixture_of, swing_statistics
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tabcase1error.json")))
 T_K, P_BAR, Z = 370.03, 16.547, [0.4, 0.6]
@@ -134,6 +134,28 @@ def test_e5_discrete_equilibrium_reproduces_table_tabcase3():
         for k, v in errs[phase].items():
             tol = 0.06 if k == "density" else 0.01
             assert abs(v - TAB3[phase][k]) <= tol, (phase, k, v, TAB3[phase][k])
+
+
+def test_e5_oracle_swing_reproduces_table_tabcase3():
+    """The oracle's own run of the case (tests/golden/e5_golden.json, written by
+    write_e5_golden.py): after the paper's 1e6 steps the liquid slab still
+    swings about a lattice-pinned position (R-26), so the printed errors are one
+    sample of that swing.  Each must lie within 3 standard deviations of the mean
+    over the 5e4 steps after 1e6 (100 samples), plus the window shift, plus 0.005
+    percentage points.  Evaluated on the stored oracle run, so rounding changes
+    in the GPU path cannot move it (the GPU is held to this run element by
+    element in test_gpu_paper_cases.py)."""
+    w = wl.WORKLOADS["e5_c1c2c3"]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "e5_golden.json")) as f:
+        gold = json.load(f)
+    assert gold["first"] == w.steps and len(gold["rows"]) == 100
+    mix = mixture_of(w)
+    for (phase, k), (mean, std, lo, hi, window) in swing_statistics(gold["rows"], mix, [0.4, 0.3, 0.3], E5_NAMES).items():
+        paper = TAB3[phase][k]
+        margin = 3 * std + window + 0.005 - abs(paper - mean)
+        print(f"{phase} {k}: paper {paper:.4f}, oracle mean {mean:.4f} std {std:.4f} range [{lo:.4f}, {hi:.4f}] "
+              f"window {window:.4f}, margin {margin:.4f}")
+        assert margin >= 0, (phase, k, paper, mean, std, window)
 
 
 # ------------------------------------------------------------ Sec. IV.D, E6
