@@ -6,10 +6,10 @@ droplets (radius 30, centres 70 apart, approaching at +-0.02) in vapor, PR EOS,
 MRT tau = 0.8, FP32 populations with FP64 EOS logarithms, and the isotropic
 lattice stencils that keep 3-D droplets in the EOS domain (the largest
 single-GPU configuration).  A step is one pass of the whole update (moments +
-EOS, interface Laplacian, force + collision + streaming) over every node;
-inputs are resident in HBM before the timed region.  The 128^3 binary slab
-(BGK tau = 0.8, the paper's axis stencils) is measured after it and reported
-under "extra_configs".
+EOS, then forces + collision + streaming) over every node; inputs are resident
+in HBM before the timed region.  The same lattice in the plain FP64 form and
+the 128^3 binary slab (BGK tau = 0.8, the paper's axis stencils) are measured
+after it and reported under "extra_configs".
 
 Prints ONE JSON line: component-MLUPS of the whole job, the roofline of the
 dominant kernel (algorithmic bytes per launch / average launch duration, HIP
@@ -428,7 +428,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched serving leg")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 128^3 binary slab after the headline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP64 form and the 128^3 binary slab after the headline")
     ap.add_argument("--serve-policy", default="largest_first", choices=["largest_first", "fifo"],
                     help="order in which arrived requests are admitted")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -522,10 +523,16 @@ def main():
         "roofline": head["roofline"],
         "mass_total": head["mass_total"],
     }
-    if not args.no_extra and args.workload != "binary_slab_3d":
-        wx = wl.WORKLOADS["binary_slab_3d"]
-        x = measure_lattice(wx, wx.precision, "axis", "workload", args.steps, args.warmup)
-        out["extra_configs"] = {"binary_slab_3d": x}
+    if not args.no_extra:
+        extra = {}
+        if precision != "fp64":
+            # the plain FP64 form of the same lattice (both forms are reported)
+            extra[f"{w.name}_fp64"] = measure_lattice(w, "fp64", stencil, args.state, args.steps, args.warmup,
+                                                      args.tuning)
+        if args.workload != "binary_slab_3d":
+            wx = wl.WORKLOADS["binary_slab_3d"]
+            extra["binary_slab_3d"] = measure_lattice(wx, wx.precision, "axis", "workload", args.steps, args.warmup)
+        out["extra_configs"] = extra
     if not args.no_serving:
         out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps,
                                        tick_ms=args.serve_tick_ms, pool_mb=args.serve_pool_mb,

@@ -184,8 +184,11 @@ void default_launch(fl_solver* s) {
     // its registers cost more than the re-reads it saves (measured on the
     // 256^3 ternary lattice).  With the isotropic stencils the plain kernel's
     // 18-neighbour gathers of seven FP64 fields set its time, and the
-    // z-marching form (which also computes -lap(phi) itself) is used.
-    lc.zmarch = p.ncomp <= 2 || p.stencil == FL_STENCIL_ISOTROPIC;
+    // z-marching form (which also computes -lap(phi) itself) is used, except
+    // with three or more components in FP64, where its collision spills
+    // (256^3 ternary: 6.59 ms against 4.58 + 0.21 ms for the plain kernel and
+    // the Laplacian pass).
+    lc.zmarch = p.ncomp <= 2 || (p.stencil == FL_STENCIL_ISOTROPIC && p.precision != FL_FP64);
     // Plain collide kernel block size: 128 threads with the interleaved layout
     // (N_c <= 2), 256 with the component-major one, whose N_c * Q streams of
     // 4 B per node read and write in longer runs per block (measured:
