@@ -430,23 +430,23 @@ int one_step(fl_solver* s, hipEvent_t* ev) {
 
 // Blocks of one launch run on XCD (block index % 8): checked once per process.
 int xcd_placement_ok(hipStream_t stream) {
-    static int verdict = -1;
-    if (verdict >= 0) return verdict;
+    static int placement = -1;
+    if (placement >= 0) return placement;
     const int nb = 4096;
     int* d = nullptr;
     std::vector<int> h(nb, -1);
-    verdict = 0;
-    if (hipMalloc(&d, nb * sizeof(int)) != hipSuccess) { (void)hipGetLastError(); return verdict; }
+    placement = 0;
+    if (hipMalloc(&d, nb * sizeof(int)) != hipSuccess) { (void)hipGetLastError(); return placement; }
     if (fl::launch_xcd_ids(d, nb, stream) == hipSuccess &&
         hipMemcpyAsync(h.data(), d, nb * sizeof(int), hipMemcpyDeviceToHost, stream) == hipSuccess &&
         hipStreamSynchronize(stream) == hipSuccess) {
-        verdict = 1;
+        placement = 1;
         for (int b = 0; b < nb; ++b)
-            if (h[b] != b % 8) verdict = 0;
+            if (h[b] != b % 8) placement = 0;
     }
     (void)hipFree(d);
     (void)hipGetLastError();
-    return verdict;
+    return placement;
 }
 
 int reduce(fl_solver* s, bool with_snap) {
