@@ -169,7 +169,7 @@ def cpu_baseline(w, stencil="axis", budget_s=12.0, single_budget_s=8.0):
 
 
 def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, plain_subset=16,
-                  tol=1e-10, check_every=1000, accuracy_subset=48, policy="largest_first"):
+                  tol=1e-10, check_every=1000, accuracy_subset=48, policy="largest_first", tuning=None):
     """Batched VLE serving: FP32-population server vs the plain FP64 path.
 
     Requests: binary D2Q9 L x 8 slabs, L log-uniform in [64, 2048], feed z1
@@ -190,6 +190,7 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, pl
     p64 = F.Params.from_workload(w, precision="fp64")
     reqs, rejected = wl.serving_requests(n=n_requests, seed=0)
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
+    srv.set_tuning(tuning)
     closed = serving.serve(srv, reqs, np.zeros(len(reqs)), tol, check_every, max_steps, tick_ms, policy=policy)
     srv.close()
     print(f"[bench] serving closed loop: {closed['converged']} of {closed['requests']} converged, "
@@ -199,6 +200,7 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, pl
     rate = 0.8 * len(recs) / span
     arrivals = serving.poisson_arrivals(len(reqs), rate, seed=0)
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
+    srv.set_tuning(tuning)
     batched = {}
     opened = serving.serve(srv, reqs, arrivals, tol, check_every, max_steps, tick_ms, policy=policy,
                            on_result=lambda rec, rho: batched.__setitem__(rec["i"], (rho, rec["steps"], rec["status"])))
@@ -226,6 +228,7 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, pl
         # (tests/test_gpu_serving.py); it solves the subset in one batch
         sub = [reqs[i] for i in acc_ids]
         srv = F.Server(p64, pool_bytes=pool_mb << 20, max_slots=512)
+        srv.set_tuning(tuning)
         ref = serving.serve(srv, sub, np.zeros(len(sub)), tol, check_every, 4 * max_steps, tick_ms,
                             on_result=lambda rec, rho: acc.__setitem__(acc_ids[rec["i"]], (rho, rec["status"])))
         srv.close()
@@ -241,6 +244,7 @@ def serving_bench(n_requests=512, max_steps=50000, pool_mb=256, tick_ms=50.0, pl
     # (one request at a time, two kernels per step)
     sub = [reqs[i] for i in conv_ids]
     srv = F.Server(p32, pool_bytes=pool_mb << 20, max_slots=512)
+    srv.set_tuning(tuning)
     cset = serving.serve(srv, sub, np.zeros(len(sub)), tol, check_every, max_steps, tick_ms, policy=policy)
     srv.close()
     idx = conv_ids[:: max(1, len(conv_ids) // plain_subset)][:plain_subset]
@@ -433,6 +437,7 @@ def main():
     ap.add_argument("--serve-policy", default="largest_first", choices=["largest_first", "fifo"],
                     help="order in which arrived requests are admitted")
     ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-tuning", default=None, help="launch tuning spec passed to fl_server_set_tuning")
     ap.add_argument("--serve-max-steps", type=int, default=50000)
     ap.add_argument("--serve-pool-mb", type=int, default=256, help="HBM budget of the server pool")
     ap.add_argument("--serve-tick-ms", type=float, default=50.0,
@@ -536,7 +541,8 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_bench(n_requests=args.serve_requests, max_steps=args.serve_max_steps,
                                        tick_ms=args.serve_tick_ms, pool_mb=args.serve_pool_mb,
-                                       policy=args.serve_policy)
+                                       policy=args.serve_policy,
+                                       tuning=args.serve_tuning)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, stencil=stencil)
     print(json.dumps(out), flush=True)

@@ -264,9 +264,12 @@ void fl_server_destroy(fl_server* srv);
 const char* fl_server_last_error(const fl_server* srv);
 
 /* Launch tuning of the server kernel, as fl_set_tuning: keys serve (threads
- * per request workgroup: 256, 512, 1024) and serve_cap (most requests
- * advanced per tick, oldest first; -1 = as many workgroups as the device holds
- * at once, 0 = all running).  Results do not depend on either.  FL_EINVAL
+ * per request workgroup: 256, 512, 1024), serve_cap (most workgroups
+ * advanced per tick, oldest request first; -1 = as many as the device holds
+ * at once, 0 = all running requests, one workgroup each) and serve_group
+ * (a request of N nodes runs on min(N / serve_group, 8) workgroups of one
+ * XCD that meet at a barrier twice per step; default 2048, 0 = one workgroup
+ * per request).  Results do not depend on any of them.  FL_EINVAL
  * (unchanged) for an unknown key or value. */
 int fl_server_set_tuning(fl_server* srv, const char* spec);
 

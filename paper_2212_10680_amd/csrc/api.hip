@@ -267,6 +267,8 @@ bool parse_tuning(LaunchCfg& lc, const char* spec, bool server) {
             t.serve_block = (int)v;
         } else if (server && key == "serve_cap" && v >= -1 && v <= 1 << 20) {
             t.serve_cap = (int)v;
+        } else if (server && key == "serve_group" && v >= 0 && v <= 1 << 24) {
+            t.serve_group = (int)v;
         } else {
             return false;
         }
@@ -926,6 +928,13 @@ struct fl_server {
     std::vector<Req> reqs;               // running or finished-not-collected
     fl::SlotDesc* d_descs = nullptr;
     fl::SlotDesc* h_descs = nullptr;
+    // per tick: block -> (request, workgroup) table and the requests' group
+    // sync blocks; capacity fixed at creation
+    int2* d_table = nullptr;
+    int2* h_table = nullptr;
+    int table_cap = 0;
+    fl::GroupSync* d_sync = nullptr;
+    int xcd_ok = -1;                     // blocks run on XCD (index % 8): checked at the first tick
     uint64_t next_id = 1;
     int wall_khz = 0;
     bool own_stream = false;
@@ -1035,6 +1044,10 @@ int fl_server_create(const fl_params* base, size_t pool_bytes, int max_slots, vo
     if (e == hipSuccess) e = hipMalloc((void**)&s->pool, s->pool_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_descs, sizeof(fl::SlotDesc) * max_slots);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_descs, sizeof(fl::SlotDesc) * max_slots, hipHostMallocDefault);
+    s->table_cap = max_slots + 8192;
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_table, sizeof(int2) * s->table_cap);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_table, sizeof(int2) * s->table_cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d_sync, sizeof(fl::GroupSync) * max_slots);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fl_server_destroy(s);
@@ -1059,6 +1072,9 @@ void fl_server_destroy(fl_server* s) {
     if (s->pool) (void)hipFree(s->pool);
     if (s->d_descs) (void)hipFree(s->d_descs);
     if (s->h_descs) (void)hipHostFree(s->h_descs);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->h_table) (void)hipHostFree(s->h_table);
+    if (s->d_sync) (void)hipFree(s->d_sync);
     if (s->own_stream && s->cfg.stream) (void)hipStreamDestroy(s->cfg.stream);
     delete s;
 }
@@ -1068,8 +1084,10 @@ const char* fl_server_last_error(const fl_server* s) { return s ? s->last_error.
 int fl_server_set_tuning(fl_server* s, const char* spec) {
     if (!s) return FL_EINVAL;
     LaunchCfg lc = s->cfg.lc;
-    lc.serve_block = 512;
-    lc.serve_cap = -1;
+    const LaunchCfg defaults{};
+    lc.serve_block = defaults.serve_block;
+    lc.serve_cap = defaults.serve_cap;
+    lc.serve_group = defaults.serve_group;
     if (spec && !parse_tuning(lc, spec, true))
         return sfail(s, FL_EINVAL, std::string("unknown tuning key or value in \"") + spec + "\"");
     SRV_TRY(s, hipStreamSynchronize(s->cfg.stream));
@@ -1157,25 +1175,72 @@ int fl_server_tick(fl_server* s, long steps, double max_ms, int* active) {
         budget = (long long)(max_ms * s->wall_khz);
         if (budget < 1) budget = 1;
     }
-    std::vector<int> run;
-    // Advance at most as many requests as the device holds workgroups at once,
-    // oldest first: a workgroup beyond that would only start when another
-    // leaves at the end of its time slice, and take the rest of the slice.
+    std::vector<int> run, groups;
+    // Advance at most as many workgroups as the device holds at once, oldest
+    // request first: a workgroup beyond that would only start when another
+    // leaves at the end of its time slice, and take the rest of the slice (and
+    // the workgroups of one request must all be resident: they wait for each
+    // other every step).
     if (s->cfg.lc.serve_cap < 0) {
         int blocks = 0;
         SRV_TRY(s, fl::serve_resident_blocks(s->cfg.lc, &blocks));
         s->cfg.lc.serve_cap = blocks > 0 ? blocks : 0;
     }
     const int cap = s->cfg.lc.serve_cap;
-    for (int k = 0; k < (int)s->reqs.size() && (cap <= 0 || (int)run.size() < cap); ++k)
-        if (s->reqs[k].d.status == fl::kSlotRunning) run.push_back(k);
+    // A request of more than serve_group nodes is split over up to kMaxGroup
+    // workgroups of one XCD (block b runs on XCD b % 8, verified once), so
+    // that its group barriers meet in one L2.
+    bool grouped = s->cfg.lc.serve_group > 0 && cap >= 8 && cap % 8 == 0;
+    if (grouped && s->xcd_ok < 0) s->xcd_ok = xcd_placement_ok(s->cfg.stream);
+    grouped = grouped && s->xcd_ok == 1;
+    int nblocks = 0;
+    if (!grouped) {
+        for (int k = 0; k < (int)s->reqs.size() && (cap <= 0 || (int)run.size() < cap); ++k)
+            if (s->reqs[k].d.status == fl::kSlotRunning) {
+                if ((int)run.size() >= s->table_cap) break;
+                s->h_table[run.size()] = make_int2((int)run.size(), 0);
+                run.push_back(k);
+                groups.push_back(1);
+            }
+        nblocks = (int)run.size();
+    } else {
+        const int per_xcd = cap / 8;
+        int used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < (int)s->reqs.size(); ++k) {
+            const fl::SlotDesc& d = s->reqs[k].d;
+            if (d.status != fl::kSlotRunning) continue;
+            const int G = std::max(1, std::min({d.N / s->cfg.lc.serve_group, fl::kMaxGroup, per_xcd}));
+            int x = -1;
+            for (int c = 0; c < 8; ++c)
+                if (per_xcd - used[c] >= G && (x < 0 || used[c] < used[x])) x = c;
+            if (x < 0) {
+                if (G == 1) break;  // every XCD is full
+                continue;           // a smaller request may still fit
+            }
+            const int i = (int)run.size();
+            for (int j = 0; j < G; ++j) s->h_table[8 * used[x]++ + x] = make_int2(i, j);
+            run.push_back(k);
+            groups.push_back(G);
+        }
+        for (int c = 0; c < 8; ++c) nblocks = std::max(nblocks, 8 * used[c]);
+        for (int c = 0; c < 8; ++c)
+            for (int u = used[c]; 8 * u + c < nblocks; ++u) s->h_table[8 * u + c] = make_int2(-1, 0);
+    }
     const int n = (int)run.size();
     if (n > 0 && steps > 0) {
-        for (int i = 0; i < n; ++i) s->h_descs[i] = s->reqs[run[i]].d;
+        bool any_group = false;
+        for (int i = 0; i < n; ++i) {
+            s->h_descs[i] = s->reqs[run[i]].d;
+            s->h_descs[i].groups = groups[i];
+            any_group = any_group || groups[i] > 1;
+        }
         fl::LaunchCfg lc = s->cfg.lc;
         lc.stream = s->cfg.stream;
         SRV_TRY(s, hipMemcpyAsync(s->d_descs, s->h_descs, sizeof(fl::SlotDesc) * n, hipMemcpyHostToDevice, lc.stream));
-        SRV_TRY(s, fl::launch_serve_tick(lc, s->cfg.kp, s->pool, s->d_descs, n, steps, budget));
+        SRV_TRY(s, hipMemcpyAsync(s->d_table, s->h_table, sizeof(int2) * nblocks, hipMemcpyHostToDevice, lc.stream));
+        if (any_group) SRV_TRY(s, hipMemsetAsync(s->d_sync, 0, sizeof(fl::GroupSync) * n, lc.stream));
+        SRV_TRY(s, fl::launch_serve_tick(lc, s->cfg.kp, s->pool, s->d_descs, s->d_table, nblocks, s->d_sync, steps,
+                                         budget));
         SRV_TRY(s, hipMemcpyAsync(s->h_descs, s->d_descs, sizeof(fl::SlotDesc) * n, hipMemcpyDeviceToHost, lc.stream));
         SRV_TRY(s, hipStreamSynchronize(lc.stream));
         const double now = host_seconds();

@@ -1549,15 +1549,47 @@ hipError_t launch_xcd_ids(int* out, int nblocks, hipStream_t stream) {
 }
 
 // ------------------------------------------------------------ batched server
-// One workgroup advances one request: the two phases of a step are separated
-// by workgroup barriers (phase B reads the densities and ln f that other
-// threads of the workgroup wrote in phase A), every thread owns the same nodes
-// in every step, and the residual check every check_every request steps is a
-// workgroup max-reduction.  Nothing depends on other requests or on where the
-// tick boundaries fall.
+// A request is advanced by one workgroup, or by G workgroups of one XCD that
+// each own a contiguous range of its nodes.  The two phases of a step are
+// separated by barriers (phase B reads the densities and ln f written in phase
+// A, phase A of the next step the populations pushed in phase B): a workgroup
+// barrier for G = 1, group_barrier across the G workgroups otherwise.  Every
+// thread owns the same nodes in every step, and the residual check every
+// check_every request steps is a max-reduction over the request.  The result
+// does not depend on G, on other requests or on where the tick boundaries fall.
+
+// Barrier across the G workgroups of one request, all on one XCD (one L2):
+// each thread's stores and atomics are complete at the L2 before the workgroup
+// counts in; after the count is reached, the CU's L1 is invalidated so that
+// loads see the other workgroups' stores (an invalidation at workgroup scope
+// leaves the L1 as it is: measured, stale neighbour values).  The wait is bounded: past the limit
+// the request is flagged failed (bad bit 2) instead of waiting on.
+constexpr long kGroupSpinLimit = 1L << 20;
+__device__ __forceinline__ void group_barrier(GroupSync* gs, unsigned& epoch, int G) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    epoch += (unsigned)G;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(&gs->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            if (++spins > kGroupSpinLimit) {
+                __hip_atomic_fetch_or(&gs->bad, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    // device-scope acquire: invalidates this CU's L1 (the L2 is shared by the
+    // group, and device memory lines stay valid there)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 template <int LAT, int NC, typename P, bool MRT, int kServeBlock>
 __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __restrict__ pool,
                                                             SlotDesc* __restrict__ descs,
+                                                            const int2* __restrict__ table, GroupSync* sync,
                                                             long long steps, long long clock_budget) {
     using L = Lat<LAT>;
     __shared__ SlotDesc sd;
@@ -1565,15 +1597,22 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
     __shared__ int s_go;
     __shared__ unsigned long long s_t0;
     __shared__ double s_red[2 * NC][kServeBlock / 64];
+    const int2 job = table[blockIdx.x];
+    if (job.x < 0) return;  // whole workgroup, before any barrier
     if (threadIdx.x == 0) {
-        sd = descs[blockIdx.x];
+        sd = descs[job.x];
         s_bad = 0;
         s_t0 = wall_clock64();
     }
     __syncthreads();
     if (sd.status != kSlotRunning) return;
+    const int G = sd.groups > 0 ? sd.groups : 1, m = job.y;
+    GroupSync* gs = sync + job.x;
+    unsigned epoch = 0;
     const Dims dm{sd.nx, sd.ny, sd.nz, sd.N};
     const size_t N = sd.N;
+    // this workgroup's nodes
+    const int lo = (int)((long long)sd.N * m / G), hi = (int)((long long)sd.N * (m + 1) / G);
     P* pops[2] = {(P*)(pool + sd.off_pop[0]), (P*)(pool + sd.off_pop[1])};
     double* rt = (double*)(pool + sd.off_rt);
     double* lnf = (double*)(pool + sd.off_lnf);
@@ -1590,27 +1629,46 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
             break;
         }
         if (clock_budget > 0 && (s & 7) == 0) {
-            // time slice, decided every 8 steps (a slice overruns its budget by
-            // at most 8 steps); every thread sees the same decision.  The next
-            // write of s_go is 8 steps and at least 16 barriers later, so no
-            // second barrier is needed before it.
-            if (threadIdx.x == 0) s_go = (long long)(wall_clock64() - s_t0) < clock_budget;
-            __syncthreads();
+            // time slice, decided every 8 steps by workgroup 0 (a slice overruns
+            // its budget by at most 8 steps); every thread of the request sees
+            // the same decision.  The next write of the decision is 8 steps and
+            // at least 16 barriers later, so no second barrier is needed before it.
+            if (G == 1) {
+                if (threadIdx.x == 0) s_go = (long long)(wall_clock64() - s_t0) < clock_budget;
+                __syncthreads();
+            } else {
+                if (m == 0 && threadIdx.x == 0)
+                    __hip_atomic_store(&gs->go, (long long)(wall_clock64() - s_t0) < clock_budget ? 1 : 0,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                group_barrier(gs, epoch, G);
+                if (threadIdx.x == 0) s_go = __hip_atomic_load(&gs->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+            }
             if (!s_go) break;
         }
         bool ok = true;
-        for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
+        for (int n = lo + threadIdx.x; n < hi; n += kServeBlock)
             ok = node_moments_eos<LAT, NC, P>(kp, n, N, pops[cur], rref, rt, lnf) && ok;
-        if (!ok) s_bad = 1;
-        __syncthreads();
+        if (G == 1) {
+            if (!ok) s_bad = 1;
+            __syncthreads();
+        } else {
+            if (!ok) __hip_atomic_fetch_or(&gs->bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            group_barrier(gs, epoch, G);
+            if (threadIdx.x == 0) s_bad = __hip_atomic_load(&gs->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
         if (s_bad) {
             status = kSlotNumeric;
             break;
         }
-        for (int n = threadIdx.x; n < dm.N; n += kServeBlock)
+        for (int n = lo + threadIdx.x; n < hi; n += kServeBlock)
             node_collide_stream<LAT, NC, P, MRT>(kp, dm, n, pops[cur], pops[1 - cur], rref, rt, lnf, fsum, fsum,
                                                  false);
-        __syncthreads();
+        if (G == 1)
+            __syncthreads();
+        else
+            group_barrier(gs, epoch, G);
         cur = 1 - cur;
         ++done;
         if (done % sd.check_every == 0) {
@@ -1618,7 +1676,7 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
             double mdiff[NC], mrho[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) mdiff[c] = mrho[c] = 0.0;
-            for (int n = threadIdx.x; n < dm.N; n += kServeBlock) {
+            for (int n = lo + threadIdx.x; n < hi; n += kServeBlock) {
                 P gv[NC][L::Q];
                 load_pops<L, NC, P>(pops[cur], n, N, gv);
                 double rho[NC], mov[NC];
@@ -1644,15 +1702,37 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
                     s_red[NC + c][wave] = mrho[c];
                 }
             __syncthreads();
+            double md[NC], mr[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                md[c] = mr[c] = 0.0;
+                for (int w = 0; w < kServeBlock / 64; ++w) {
+                    md[c] = fmax(md[c], s_red[c][w]);
+                    mr[c] = fmax(mr[c], s_red[NC + c][w]);
+                }
+            }
+            if (G > 1) {
+                // the request's maxima from every workgroup's
+                if (threadIdx.x == 0)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        gs->part[m][c] = md[c];
+                        gs->part[m][NC + c] = mr[c];
+                    }
+                group_barrier(gs, epoch, G);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    md[c] = mr[c] = 0.0;
+                    for (int k = 0; k < G; ++k) {
+                        md[c] = fmax(md[c], gs->part[k][c]);
+                        mr[c] = fmax(mr[c], gs->part[k][NC + c]);
+                    }
+                }
+            }
             double r = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                double md = 0.0, mr = 0.0;
-                for (int w = 0; w < kServeBlock / 64; ++w) {
-                    md = fmax(md, s_red[c][w]);
-                    mr = fmax(mr, s_red[NC + c][w]);
-                }
-                const double rc = md / ((double)sd.check_every * mr);
+                const double rc = md[c] / ((double)sd.check_every * mr[c]);
                 r = (rc > r || rc != rc) ? rc : r;
             }
             residual = r;
@@ -1668,11 +1748,13 @@ __global__ __launch_bounds__(kServeBlock) void k_serve_tick(KParams kp, char* __
         }
     }
     if (status == kSlotRunning && done >= sd.max_steps) status = kSlotMaxSteps;
-    if (threadIdx.x == 0) {
-        descs[blockIdx.x].steps = done;
-        descs[blockIdx.x].cur = cur;
-        descs[blockIdx.x].residual = residual;
-        descs[blockIdx.x].status = status;
+    if (G > 1 && status == kSlotRunning && (__hip_atomic_load(&gs->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
+        status = kSlotNumeric;  // a group barrier timed out
+    if (m == 0 && threadIdx.x == 0) {
+        descs[job.x].steps = done;
+        descs[job.x].cur = cur;
+        descs[job.x].residual = residual;
+        descs[job.x].status = status;
     }
 }
 
@@ -1700,17 +1782,20 @@ hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks) {
     return e;
 }
 
-hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs, int nslots,
-                             long long steps, long long clock_budget) {
-    if (nslots <= 0) return hipSuccess;
+hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs,
+                             const int2* table, int nblocks, GroupSync* sync, long long steps,
+                             long long clock_budget) {
+    if (nblocks <= 0) return hipSuccess;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         auto go = [&](auto bsc) {
             constexpr int BS = decltype(bsc)::value;
             if (lc.mrt)
-                k_serve_tick<LAT, NC, P, true, BS><<<nslots, BS, 0, lc.stream>>>(kp, pool, descs, steps, clock_budget);
+                k_serve_tick<LAT, NC, P, true, BS><<<nblocks, BS, 0, lc.stream>>>(kp, pool, descs, table, sync, steps,
+                                                                                 clock_budget);
             else
-                k_serve_tick<LAT, NC, P, false, BS><<<nslots, BS, 0, lc.stream>>>(kp, pool, descs, steps, clock_budget);
+                k_serve_tick<LAT, NC, P, false, BS><<<nblocks, BS, 0, lc.stream>>>(kp, pool, descs, table, sync, steps,
+                                                                                  clock_budget);
         };
         if (lc.serve_block >= 1024)
             go(std::integral_constant<int, 1024>{});

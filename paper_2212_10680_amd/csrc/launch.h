@@ -19,8 +19,10 @@ struct LaunchCfg {
     bool xcd_remap_k2 = true;  // the same for the plain collide/stream kernel
     bool nt_store = false;  // non-temporal population stores
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
-    int serve_cap = -1;     // most requests advanced per tick, oldest first
+    int serve_cap = -1;     // most workgroups advanced per tick, oldest request first
                             // (-1: as many as the device holds at once, 0: all running)
+    int serve_group = 2048; // nodes per workgroup at which a request is split over several
+                            // workgroups of one XCD (0: one workgroup per request)
     bool fused = false;     // one-launch step (fl_set_tuning "fused=1") when the lattice allows it
     bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (set per solver)
     bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
@@ -89,15 +91,34 @@ struct SlotDesc {
     double residual;
     int cur;                  // population buffer holding the current state
     int status;               // kSlotRunning, kSlotConverged, kSlotMaxSteps, kSlotNumeric
+    int groups;               // workgroups advancing this request in the tick (1..kMaxGroup)
+    int pad;
 };
 enum { kSlotRunning = 0, kSlotConverged = 1, kSlotMaxSteps = 2, kSlotNumeric = 3 };
 
+// Workgroups of one request share this block of device memory during a tick
+// (zeroed before it): barrier arrivals, the time-slice decision of workgroup
+// 0, a numeric-failure flag, and each workgroup's residual maxima.
+constexpr int kMaxGroup = 8;
+struct GroupSync {
+    unsigned count;
+    int go;
+    int bad;
+    int pad;
+    double part[kMaxGroup][2 * kMaxComp];
+};
+// Block b of a tick advances request table[b].x as its workgroup table[b].y
+// (table[b].x < 0: the block has no work).
+
 // Workgroups of the batched-server kernel that the device holds at once.
 hipError_t serve_resident_blocks(const LaunchCfg& lc, int* blocks);
-// Advance every slot of descs[0..nslots) by up to `steps` steps, one workgroup
-// per slot, each stopping early once clock_budget ticks of the device wall
-// clock have passed (<= 0: no limit); descs is updated in place.
+// Advance every request of descs by up to `steps` steps with `nblocks`
+// workgroups mapped by table (the groups[] workgroups of a request on one
+// XCD, all resident at once), each request stopping early once clock_budget
+// ticks of the device wall clock have passed (<= 0: no limit); descs is
+// updated in place, sync holds one GroupSync per request.
 hipError_t launch_serve_tick(const LaunchCfg& lc, const KParams& kp, char* pool, SlotDesc* descs,
-                             int nslots, long long steps, long long clock_budget);
+                             const int2* table, int nblocks, GroupSync* sync, long long steps,
+                             long long clock_budget);
 
 }  // namespace fl

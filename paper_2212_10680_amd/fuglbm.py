@@ -353,7 +353,7 @@ class Server:
             pass
 
     def set_tuning(self, spec=None):
-        """Server launch tuning (fl_server_set_tuning): serve, serve_cap."""
+        """Server launch tuning (fl_server_set_tuning): serve, serve_cap, serve_group."""
         arg = None if spec is None else spec.encode()
         self._check(self.lib.fl_server_set_tuning(self.h, arg), "fl_server_set_tuning")
 

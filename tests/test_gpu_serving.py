@@ -184,3 +184,61 @@ def test_request_cap_per_tick_bitwise():
         a, b = capped[i], free[i]
         assert a[1] == b[1] and a[2] == b[2] and a[3] == b[3], i
         assert np.array_equal(a[0], b[0]), i
+
+
+def run_server_ms(p, reqs, tol, check, max_steps, tick, max_ms, tune):
+    """run_server with time-sliced ticks (tick steps or max_ms of device time)."""
+    srv = F.Server(p, pool_bytes=1 << 28, max_slots=64)
+    srv.set_tuning(tune)
+    ids = {}
+    for i, r in enumerate(reqs):
+        rid = srv.submit(serving.request_field(r), (r["L"], r["ny"]), tol, check, max_steps)
+        assert rid is not None
+        ids[rid] = i
+    out = {}
+    while len(out) < len(reqs):
+        srv.tick(tick, max_ms)
+        for rid in srv.poll():
+            i = ids[rid]
+            out[i] = srv.result(rid, reqs[i]["L"] * reqs[i]["ny"])
+    srv.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_workgroup_groups_bitwise(precision):
+    """Requests split over several workgroups of one XCD (serve_group: nodes
+    per workgroup; groups of up to 8 that meet at a barrier twice per step)
+    give the same result bit for bit as one workgroup per request: ten
+    requests of 256 to 1 280 nodes at serve_group = 128 (groups of 2 to 8),
+    with residual checks, converged and capped requests, and both with whole
+    ticks and with ticks cut by a device-time budget."""
+    announce(f"workgroup groups vs one workgroup per request ({precision})")
+    p = base_params(precision)
+    reqs = some_requests(10, seed=3)
+    ref = run_server(p, reqs, tol=3e-6, check=100, max_steps=3000, tick=700, tune="serve_group=0")
+    got = run_server(p, reqs, tol=3e-6, check=100, max_steps=3000, tick=700, tune="serve_group=128")
+    sliced = run_server_ms(p, reqs, tol=3e-6, check=100, max_steps=3000, tick=5000, max_ms=0.3,
+                           tune="serve_group=128")
+    statuses = set()
+    for i in range(len(reqs)):
+        statuses.add(ref[i][3])
+        for g in (got[i], sliced[i]):
+            assert np.array_equal(ref[i][0], g[0]), i
+            assert ref[i][1:] == g[1:], (i, ref[i][1:], g[1:])
+    print(f"  statuses {sorted(statuses)}, steps {[ref[i][1] for i in range(len(reqs))]}", flush=True)
+
+
+def test_workgroup_groups_fill_and_wait():
+    """Grouped workgroups filling the device: 48 requests of 2 048 nodes in
+    groups of 8 (a tick places groups while an XCD has room for one, at most
+    the workgroups the device holds at once, the rest wait for later ticks);
+    results bitwise equal to one workgroup per request."""
+    announce("workgroup groups filling the device")
+    p = base_params("fp32")
+    reqs = [dict(r, L=256) for r in some_requests(48, seed=5)]
+    ref = run_server(p, reqs, tol=0.0, check=200, max_steps=600, tick=250, tune="serve_group=0")
+    got = run_server(p, reqs, tol=0.0, check=200, max_steps=600, tick=250, tune="serve_group=256")
+    for i in range(len(reqs)):
+        assert np.array_equal(ref[i][0], got[i][0]), i
+        assert ref[i][1:] == got[i][1:], i
