@@ -268,7 +268,7 @@ const char* fl_server_last_error(const fl_server* srv);
  * advanced per tick, oldest request first; -1 = as many as the device holds
  * at once, 0 = all running requests, one workgroup each) and serve_group
  * (a request of N nodes runs on min(N / serve_group, 8) workgroups of one
- * XCD that meet at a barrier twice per step; default 2048, 0 = one workgroup
+ * XCD that meet at a barrier twice per step; default 3584, 0 = one workgroup
  * per request).  Results do not depend on any of them.  FL_EINVAL
  * (unchanged) for an unknown key or value. */
 int fl_server_set_tuning(fl_server* srv, const char* spec);

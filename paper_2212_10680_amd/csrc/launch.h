@@ -21,7 +21,7 @@ struct LaunchCfg {
     int serve_block = 512;  // threads per request in the batched server (256, 512, 1024)
     int serve_cap = -1;     // most workgroups advanced per tick, oldest request first
                             // (-1: as many as the device holds at once, 0: all running)
-    int serve_group = 2048; // nodes per workgroup at which a request is split over several
+    int serve_group = 3584; // nodes per workgroup at which a request is split over several
                             // workgroups of one XCD (0: one workgroup per request)
     bool fused = false;     // one-launch step (fl_set_tuning "fused=1") when the lattice allows it
     bool zmarch = false;    // z-marching collide/stream kernel where zmarch_fits() (set per solver)
