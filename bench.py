@@ -62,8 +62,9 @@ def algorithmic_bytes(w, precision, stencil="axis", lap_pass=None):
     (D values).  The FP32 form also reads the rest-population reference.
     k_interface_lap (isotropic stencils, when the collide pass is the
     one-thread-per-node kernel): read phi, write -lap(phi).
-    k_collide_zmarch_iso (isotropic stencils, z-marching): reads phi instead of
-    -lap(phi), which it forms itself; no Laplacian pass then runs.
+    k_collide_zmarch_iso (isotropic stencils, z-marching; with three components
+    k_collide_zmarch_iso_cs, one thread group per component): reads phi instead
+    of -lap(phi), which it forms itself; no Laplacian pass then runs.
     k_fused_step: the whole step, i.e. the per-node-step figure.
     """
     Q = 9 if w.lattice == "D2Q9" else 19
@@ -84,6 +85,7 @@ def algorithmic_bytes(w, precision, stencil="axis", lap_pass=None):
     # and with the isotropic stencils the Laplacian pass (phi in, -lap(phi) out)
     step = 2 * pops + 2 * aux + 2 * s * D + ref + lap
     out = {"k_moments_eos": k1, "k_collide_stream": k2, "k_collide_zmarch": k2, "k_collide_zmarch_iso": k2,
+           "k_collide_zmarch_iso_cs": k2,
            "k_fused_step": step, "step": step}
     if lap:
         out["k_interface_lap"] = lap

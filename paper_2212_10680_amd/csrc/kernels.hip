@@ -74,19 +74,34 @@ __device__ __forceinline__ void load_pops(const P* __restrict__ g, int n, size_t
 
 // rho_i = sum_a g_ai (step 1), accumulated in FP64; also sum of the moving ones.
 // ref[c] is the node's rest-population reference (FP32 form; unused in FP64).
+template <typename L, typename P>
+__device__ __forceinline__ void comp_density(const P (&gv)[L::Q], float ref, double& rho, double& moving) {
+    double m = 0.0;
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a) m += (double)gv[a];
+    double r0 = (double)gv[0];
+    if constexpr (sizeof(P) == 4) r0 += (double)ref;
+    moving = m;
+    rho = r0 + m;
+}
+
 template <typename L, int NC, typename P>
 __device__ __forceinline__ void densities_ref(const P (&gv)[NC][L::Q], const float (&ref)[NC], double (&rho)[NC],
                                               double (&moving)[NC]) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double m = 0.0;
-#pragma unroll
-        for (int a = 1; a < L::Q; ++a) m += (double)gv[c][a];
-        double r0 = (double)gv[c][0];
-        if constexpr (sizeof(P) == 4) r0 += (double)ref[c];
-        moving[c] = m;
-        rho[c] = r0 + m;
-    }
+    for (int c = 0; c < NC; ++c) comp_density<L, P>(gv[c], ref[c], rho[c], moving[c]);
+}
+
+// Momentum sum_a e_a g_a of one component in FP64 (step 1).
+template <typename L, typename P>
+__device__ __forceinline__ void comp_momentum(const P (&gv)[L::Q], double (&j)[3]) {
+    j[0] = j[1] = j[2] = 0.0;
+    Unroll<0, L::Q>::run([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        if constexpr (L::ex[a] != 0) j[0] += (double)gv[a] * L::ex[a];
+        if constexpr (L::ey[a] != 0) j[1] += (double)gv[a] * L::ey[a];
+        if constexpr (L::ez[a] != 0) j[2] += (double)gv[a] * L::ez[a];
+    });
 }
 
 template <int NC, typename P>
@@ -368,6 +383,23 @@ __device__ __forceinline__ void iso_grad(double px, double py, double bm, const 
 // F_i = -rho~_i grad(mu_i), grad rho_i = M_i grad(rho~_i) (step 7), from the
 // gradients of mu_i and rho~_i and the node's rho~_i, kept in the collision
 // precision T; their sum over components in FP64.
+// One component i: f = F_i in FP64 (summed over components by the caller), F_i
+// and grad rho_i in T.
+template <typename T>
+__device__ __forceinline__ void comp_force(const KParams& kp, int i, const double (&gmu)[3], const double (&grt)[3],
+                                           double rc, double (&f)[3], T (&F)[3], T (&G)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double fk = -(rc * gmu[k]);
+        const double gr = kp.M[i] * grt[k];
+        if constexpr (sizeof(T) == 8)
+            if (kp.standard) fk += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
+        f[k] = fk;
+        F[k] = T(fk);
+        G[k] = T(gr);
+    }
+}
+
 template <int NC, typename T>
 __device__ __forceinline__ void force_from_grads(const KParams& kp, const double (&gmu)[NC][3],
                                                  const double (&grt)[NC][3], const double (&rc)[NC],
@@ -375,17 +407,12 @@ __device__ __forceinline__ void force_from_grads(const KParams& kp, const double
 #pragma unroll
     for (int k = 0; k < 3; ++k) Fs[k] = 0.0;
 #pragma unroll
-    for (int i = 0; i < NC; ++i)
+    for (int i = 0; i < NC; ++i) {
+        double f[3];
+        comp_force<T>(kp, i, gmu[i], grt[i], rc[i], f, F[i], G[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double f = -(rc[i] * gmu[i][k]);
-            const double gr = kp.M[i] * grt[i][k];
-            if constexpr (sizeof(T) == 8)
-                if (kp.standard) f += gr / 3.0;  // eqForceGen: + c_s^2 grad rho_i
-            Fs[k] += f;
-            F[i][k] = T(f);
-            G[i][k] = T(gr);
-        }
+        for (int k = 0; k < 3; ++k) Fs[k] += f[k];
+    }
 }
 
 // Steps 6-7 at one node of a D3Q19 lattice with the isotropic stencils, from
@@ -493,10 +520,89 @@ __device__ __forceinline__ void load_node_inputs(const P* __restrict__ g, const 
     load_ref<NC, P>(rref, n, in.ref);
 }
 
+// Periodic neighbour n + e of node n = (x, y, z) as n plus per-axis steps
+// (wrapped at the faces); off() gives the byte offset of its populations.
+template <int D, int NC, typename P>
+struct PushGeom {
+    int n;
+    int step[3][2];
+    __device__ __forceinline__ PushGeom(const Dims& dm, int n_, int x, int y, int z) : n(n_) {
+        const int nx = dm.nx, sy = dm.nx, sz = dm.nx * dm.ny;
+        step[0][0] = x == 0 ? nx - 1 : -1;
+        step[0][1] = x == nx - 1 ? 1 - nx : 1;
+        step[1][0] = y == 0 ? (dm.ny - 1) * sy : -sy;
+        step[1][1] = y == dm.ny - 1 ? (1 - dm.ny) * sy : sy;
+        step[2][0] = z == 0 ? (dm.nz - 1) * sz : -sz;
+        step[2][1] = z == dm.nz - 1 ? (1 - dm.nz) * sz : sz;
+    }
+    __device__ __forceinline__ unsigned off(int dx, int dy, int dz) const {
+        int m = n;
+        if (dx) m += step[0][dx > 0];
+        if (dy) m += step[1][dy > 0];
+        if (D == 3 && dz) m += step[2][dz > 0];
+        return pop_off<NC, P>(m);
+    }
+};
+
+// Step 1's velocity from the node's densities rho_i and momentum j (FP64) and
+// the force of the chosen time level: this step's sum Fs or the previous
+// step's fprev.
+template <int D, typename P>
+__device__ __forceinline__ void node_velocity(const KParams& kp, double rtot, const double (&j)[3],
+                                              const double (&Fs)[3], const P (&fprev)[3], double (&u)[3]) {
+    u[0] = u[1] = u[2] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double fk = kp.force_level ? Fs[k] : (double)fprev[k];
+        u[k] = (j[k] + 0.5 * fk) / rtot;
+    }
+}
+
+// Steps 8-9 of component c at a node: equilibrium, forcing and collision of
+// its populations gv (stored convention, see collide), result in oc.
+template <typename L, typename P, bool MRT>
+__device__ __forceinline__ void collide_comp(const KParams& kp, const P (&gv)[L::Q], double rho, double mov,
+                                             const double (&u)[3], const P (&F)[3], const P (&G)[3],
+                                             P (&oc)[L::Q]) {
+    using T = P;  // collision precision
+    CompState<T> cs;
+    cs.rho = T(rho);
+    cs.ux = T(u[0]); cs.uy = T(u[1]); cs.uz = T(u[2]);
+    cs.Fx = F[0]; cs.Fy = F[1]; cs.Fz = F[2];
+    cs.Gx = G[0]; cs.Gy = G[1]; cs.Gz = G[2];
+    bool std_form = false;
+    if constexpr (sizeof(P) == 8) std_form = kp.standard != 0;
+    if constexpr (sizeof(P) == 8) {
+        if (std_form) {
+            cs.Gx = cs.Gy = cs.Gz = T(0);  // Guo forcing without the grad rho part
+            collide<L, T, MRT, false, true>(kp, cs, gv, T(mov), oc);
+        }
+    }
+    if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv, T(mov), oc);
+}
+
+// Push of component c's post-collision populations to n + e_a of gn
+// (component-major layout).
+template <typename L, int NC, typename P>
+__device__ __forceinline__ void push_comp(const PushGeom<L::D, NC, P>& pg, P* __restrict__ gn, int c, size_t N,
+                                          const P (&o)[L::Q], bool nt) {
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+        P* dst = pop_base<NC, L::Q>(gn, c, a, N);
+        const unsigned off = pg.off(L::ex[a], L::ey[a], L::ez[a]);
+        if (nt)
+            __builtin_nontemporal_store(o[a], (P*)((char*)dst + off));
+        else
+            st(dst, off, o[a]);
+    }
+}
+
 // Steps 8-9 (and step 1's velocity) at node n = (x, y, z) from its loaded
 // inputs (gv, fprev): moments of the node's populations, u with the force of
 // the chosen time level, equilibrium, forcing and collision per component, push
-// streaming to n + e_a of gn.
+// streaming to n + e_a of gn.  The momentum is summed component by component
+// for N_c >= 3 (each component's sum first, then their sum in order), so a
+// kernel that gives each component to its own threads forms the same bits.
 template <int LAT, int NC, typename P, bool MRT>
 __device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dims& dm, int n, int x, int y, int z,
                                                     const NodeIn<LAT, NC, P>& in, P* __restrict__ gn,
@@ -504,22 +610,10 @@ __device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dim
                                                     const double (&Fs)[3], P* fsum_out, bool nt) {
     using L = Lat<LAT>;
     const auto& gv = in.gv;
-    const auto& fprev = in.fprev;
     constexpr int D = L::D, Q = L::Q;
     using T = P;  // collision precision
     const size_t N = dm.N;
-    // periodic neighbour n + e_a as n plus per-axis steps (wrapped at the faces)
-    const int nx = dm.nx, sy = dm.nx, sz = dm.nx * dm.ny;
-    const int step[3][2] = {{x == 0 ? nx - 1 : -1, x == nx - 1 ? 1 - nx : 1},
-                            {y == 0 ? (dm.ny - 1) * sy : -sy, y == dm.ny - 1 ? (1 - dm.ny) * sy : sy},
-                            {z == 0 ? (dm.nz - 1) * sz : -sz, z == dm.nz - 1 ? (1 - dm.nz) * sz : sz}};
-    auto nbr_off = [&](int dx, int dy, int dz) {
-        int m = n;
-        if (dx) m += step[0][dx > 0];
-        if (dy) m += step[1][dy > 0];
-        if (D == 3 && dz) m += step[2][dz > 0];
-        return pop_off<NC, P>(m);   // byte offset of node m's populations
-    };
+    const PushGeom<D, NC, P> pg(dm, n, x, y, z);
 
     double rho[NC], mov[NC];
     densities_ref<L, NC, P>(gv, in.ref, rho, mov);
@@ -527,53 +621,32 @@ __device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dim
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         rtot += rho[c];
+        if constexpr (NC >= 3) {
+            double jc[3];
+            comp_momentum<L, P>(gv[c], jc);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            j[0] += (double)gv[c][a] * L::ex[a];
-            j[1] += (double)gv[c][a] * L::ey[a];
-            j[2] += (double)gv[c][a] * L::ez[a];
+            for (int k = 0; k < 3; ++k) j[k] += jc[k];
+        } else {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                j[0] += (double)gv[c][a] * L::ex[a];
+                j[1] += (double)gv[c][a] * L::ey[a];
+                j[2] += (double)gv[c][a] * L::ez[a];
+            }
         }
     }
-    double u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const double fk = kp.force_level ? Fs[k] : (double)fprev[k];
-        u[k] = (j[k] + 0.5 * fk) / rtot;
-    }
+    double u[3];
+    node_velocity<D, P>(kp, rtot, j, Fs, in.fprev, u);
     // Push: direction a goes to n + e_a.  With the interleaved layout (N_c <= 2)
     // both values of a direction leave as one vector store (all outputs live
     // at once); with more components each is stored right after its collision.
     constexpr bool kJoint = kInterleaved<NC>;
     T out[kJoint ? NC : 1][Q];
-    auto push = [&](int c, const T (&o)[Q]) {
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            P* dst = pop_base<NC, Q>(gn, c, a, N);
-            const unsigned off = nbr_off(L::ex[a], L::ey[a], L::ez[a]);
-            if (nt)
-                __builtin_nontemporal_store(o[a], (P*)((char*)dst + off));
-            else
-                st(dst, off, o[a]);
-        }
-    };
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        CompState<T> cs;
-        cs.rho = T(rho[c]);
-        cs.ux = T(u[0]); cs.uy = T(u[1]); cs.uz = T(u[2]);
-        cs.Fx = F[c][0]; cs.Fy = F[c][1]; cs.Fz = F[c][2];
-        cs.Gx = G[c][0]; cs.Gy = G[c][1]; cs.Gz = G[c][2];
         T (&oc)[Q] = out[kJoint ? c : 0];
-        bool std_form = false;
-        if constexpr (sizeof(P) == 8) std_form = kp.standard != 0;
-        if constexpr (sizeof(P) == 8) {
-            if (std_form) {
-                cs.Gx = cs.Gy = cs.Gz = T(0);  // Guo forcing without the grad rho part
-                collide<L, T, MRT, false, true>(kp, cs, gv[c], T(mov[c]), oc);
-            }
-        }
-        if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv[c], T(mov[c]), oc);
-        if constexpr (!kJoint) push(c, oc);
+        collide_comp<L, P, MRT>(kp, gv[c], rho[c], mov[c], u, F[c], G[c], oc);
+        if constexpr (!kJoint) push_comp<L, NC, P>(pg, gn, c, N, oc, nt);
     }
     if constexpr (kJoint) {
         using V = P __attribute__((ext_vector_type(NC)));
@@ -583,7 +656,7 @@ __device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dim
 #pragma unroll
             for (int c = 0; c < NC; ++c) v[c] = out[c][a];
             V* dst = reinterpret_cast<V*>(reinterpret_cast<char*>(pop_base<NC, Q>(gn, 0, a, N)) +
-                                          nbr_off(L::ex[a], L::ey[a], L::ez[a]));
+                                          pg.off(L::ex[a], L::ey[a], L::ez[a]));
             if (nt)
                 __builtin_nontemporal_store(v, dst);
             else
@@ -887,11 +960,42 @@ constexpr int kZmarchIsoWaves = (sizeof(P) == 4 && NC == 1) ? 2 : 1;
 
 __device__ __forceinline__ int mod3(int q) { return ((q % 3) + 3) % 3; }
 
+// The tile (txy) and z-range (zc) of z-marching workgroup b, or false for a
+// workgroup with no work.  Hardware block b runs on XCD b % 8.
+//   zorder 0: XCD-contiguous chunks: XCD k takes the logical blocks
+//             k * xcd_chunk .. (k + 1) * xcd_chunk - 1 (tiles fastest, then
+//             z-ranges; xcd_chunk = 0: logical block b);
+//   zorder 1: XCD y-bands: the tile rows are cut into 8 bands of at most
+//             ceil(tiles_y / 8) rows, XCD k takes band k of every z-range,
+//             z-ranges in order, so that all XCDs march through the same planes
+//             at once (the DRAM pages of every stream then open for one window
+//             of addresses instead of eight) and a band's halo planes, read
+//             again by its next z-range, stay in its XCD's L2.  The grid is
+//             zmarch_grid() blocks; a shorter band leaves blocks idle.
+__device__ __forceinline__ bool zmarch_tile_of_block(int b, int tiles_x, int tiles_y, int nzc, int xcd_chunk,
+                                                     int zorder, int& zc, int& txy) {
+    if (zorder == 1) {
+        const int k = b & 7, j = b >> 3;
+        const int rows = (tiles_y + 7) >> 3;           // tile rows per band, at most
+        const int per = rows * tiles_x;                 // blocks per band and z-range
+        zc = j / per;
+        const int tl = j - zc * per;
+        const int r0 = (k * tiles_y) >> 3, r1 = ((k + 1) * tiles_y) >> 3;
+        const int ty = r0 + tl / tiles_x;
+        txy = ty * tiles_x + tl % tiles_x;
+        return zc < nzc && ty < r1;
+    }
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    zc = lb / (tiles_x * tiles_y);
+    txy = lb - zc * tiles_x * tiles_y;
+    return lb < tiles_x * tiles_y * nzc;
+}
+
 template <int NC, typename P, bool MRT>
 __global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarch_iso(
     KParams kp, const P* __restrict__ g, P* __restrict__ gn, const float* __restrict__ rref,
     const double* __restrict__ rt, const double* __restrict__ lnf, const P* fsum_in, P* fsum_out, int zlen,
-    int xcd_chunk, int nt) {
+    int xcd_chunk, int nt, int zorder) {
     constexpr int NF = 2 * NC;  // fields: mu_i, then rho~_i
     const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
     const size_t N = kp.N;
@@ -899,10 +1003,9 @@ __global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarc
     const int tiles_x = nx / kZX;
     const int tiles_xy = tiles_x * (ny / kZY);
     const int nzc = (nz + zlen - 1) / zlen;
-    const int b = blockIdx.x;
-    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
-    if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
-    const int zc = lb / tiles_xy, txy = lb - zc * tiles_xy;
+    int zc, txy;
+    if (!zmarch_tile_of_block(blockIdx.x, tiles_x, tiles_xy / tiles_x, nzc, xcd_chunk, zorder, zc, txy))
+        return;  // whole workgroup, before any barrier
     const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
     const int t = threadIdx.x;
@@ -1026,6 +1129,208 @@ __global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarc
         if (ring) store_phi(z + 4, fp);
         collide_push_loaded<1, NC, P, MRT>(kp, dm, col + z * plane, x, y, z, in, gn, F, G, Fs, fsum_out, nt != 0);
         __syncthreads();
+    }
+}
+
+// ------------- steps 6-9, z-marching form, isotropic stencils, one component per thread group
+// The same tile, rings and stencil as k_collide_zmarch_iso, for the
+// component-major layout (N_c >= 3), with the work of a node split by
+// component: the workgroup has N_c groups of 256 threads and group c owns
+// component c of every node of the tile.  A group reads its component's Q
+// population streams, forms mu_c and rho~_c of the planes it fills, the
+// stencil and force of component c, its density and momentum, and collides
+// and pushes component c.  The velocity needs every component's density and
+// momentum and the force sum every component's force: each group writes its
+// seven FP64 values per node to LDS before the first barrier of a plane and
+// reads the others' after it, summing in component order, so the result is
+// the same bit for bit as the kernels that keep a node in one thread.  A
+// thread then holds one component's collision instead of N_c: at three
+// components 768 threads, three waves per SIMD, where the one-thread-per-node
+// z-march needs more than 256 registers per lane and runs one.
+template <int NC, typename P, bool MRT>
+__global__ __launch_bounds__(256 * NC) void k_collide_zmarch_iso_cs(
+    KParams kp, const P* __restrict__ g, P* __restrict__ gn, const float* __restrict__ rref,
+    const double* __restrict__ rt, const double* __restrict__ lnf, const P* fsum_in, P* fsum_out, int zlen,
+    int xcd_chunk, int nt, int zorder) {
+    static_assert(!kInterleaved<NC>, "component-major layout only");
+    static_assert(kPhiPts <= 256 * NC, "one phi fill point per thread");
+    using L = Lat<1>;
+    constexpr int Q = L::Q;
+    constexpr int kX = 7;  // exchanged per node and component: rho, j (3), f (3)
+    const int nx = kp.nx, ny = kp.ny, nz = kp.nz;
+    const size_t N = kp.N;
+    const int plane = nx * ny;
+    const int tiles_x = nx / kZX;
+    const int tiles_xy = tiles_x * (ny / kZY);
+    const int nzc = (nz + zlen - 1) / zlen;
+    int zc, txy;
+    if (!zmarch_tile_of_block(blockIdx.x, tiles_x, tiles_xy / tiles_x, nzc, xcd_chunk, zorder, zc, txy))
+        return;  // whole workgroup, before any barrier
+    const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
+    const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
+    const int tg = threadIdx.x;
+    // this thread's component: uniform over a wave (256 is a multiple of 64),
+    // taken into a scalar register so that its addresses are scalar too
+    const int c = __builtin_amdgcn_readfirstlane(tg >> 8);
+    const int t = tg & 255;      // this thread's node in the tile
+    const int tx = t % kZX, ty = t / kZX;
+    const int x = x0 + tx, y = y0 + ty;
+    const int col = x + nx * y;
+    const Dims dm{nx, ny, nz, kp.N};
+    const double* phig = lnf + (size_t)NC * N;
+    const double* lnf_c = lnf + (size_t)c * N;
+    const double* rt_c = rt + (size_t)c * N;
+
+    __shared__ double s_phi[4][kPhiPts];   // phi plane q in slot q & 3
+    __shared__ double s_f[3][2 * NC][kRlPts];  // mu_i, rho~_i of plane q in buffer q mod 3
+    __shared__ double s_x[NC][kX][256];    // per-node exchange between the groups
+
+    // fill pattern: one phi point per thread (the whole workgroup), and
+    // kRlPer points of its own component's mu and rho~ per thread of a group
+    const bool phi_fill = tg < kPhiPts;
+    const unsigned phi_off =
+        phi_fill ? 8u * (unsigned)(wrap2(x0 - 2 + tg % kPhiW, nx) + nx * wrap2(y0 - 2 + tg / kPhiW, ny)) : 0u;
+    unsigned rl_off[kRlPer];
+#pragma unroll
+    for (int k = 0; k < kRlPer; ++k) {
+        const int q = t + 256 * k;
+        rl_off[k] = q < kRlPts ? 8u * (unsigned)(wrap2(x0 - 1 + q % kRlW, nx) + nx * wrap2(y0 - 1 + q / kRlW, ny)) : 0u;
+    }
+    auto rl_fills = [&](int k) { return k < kRlPer - 1 || t + 256 * k < kRlPts; };
+    auto zoff = [&](int zz) { return (size_t)wrap2(zz, nz) * plane; };
+    auto load_phi = [&](int q) { return ld(phig + zoff(q), phi_off); };
+    auto store_phi = [&](int q, double v) {
+        if (phi_fill) s_phi[q & 3][tg] = v;
+    };
+    // ln f_c and rho~_c of plane q at this thread's fill points
+    auto load_fill = [&](int q, double (&v)[2][kRlPer]) {
+        const size_t zo = zoff(q);
+#pragma unroll
+        for (int k = 0; k < kRlPer; ++k) {
+            v[0][k] = ld(lnf_c + zo, rl_off[k]);
+            v[1][k] = ld(rt_c + zo, rl_off[k]);
+        }
+    };
+    // mu_c and rho~_c of plane q into its buffer (phi planes q-1 .. q+1 in the ring)
+    auto store_fill = [&](int q, const double (&v)[2][kRlPer]) {
+        const int bq = mod3(q);
+#pragma unroll
+        for (int k = 0; k < kRlPer; ++k) {
+            if (!rl_fills(k)) continue;
+            const int pt = t + 256 * k;
+            const int bx = pt % kRlW + 1, by = pt / kRlW + 1;  // in the phi box
+            const double mh = neg_lap_iso<1>([&](int dx, int dy, int dz) {
+                return s_phi[(q + dz) & 3][(by + dy) * kPhiW + bx + dx];
+            });
+            s_f[bq][c][pt] = chem_pot(kp, c, v[0][k], mh);
+            s_f[bq][NC + c][pt] = v[1][k];
+        }
+    };
+    // component c's inputs of node plane zz: populations, rest reference, the
+    // previous step's force sum
+    P gv[Q], fprev[3];
+    float ref = 0.f;
+    auto load_inputs = [&](int zz) {
+        const int n = col + zz * plane;
+        const unsigned off = pop_off<NC, P>(n);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fprev[k] = ld(fsum_in, ((unsigned)n * 3 + k) * (unsigned)sizeof(P));
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+            gv[a] = __builtin_nontemporal_load(reinterpret_cast<const P*>(
+                reinterpret_cast<const char*>(pop_base<NC, Q>(g, c, a, N)) + off));
+        if constexpr (sizeof(P) == 4) ref = ld(rref, ((unsigned)n * NC + c) * 4u);
+    };
+
+    // prologue, as in k_collide_zmarch_iso
+    {
+        double v[2][kRlPer], w[2][kRlPer];
+#pragma unroll
+        for (int d = -2; d <= 1; ++d) store_phi(z0 + d, load_phi(z0 + d));
+        load_fill(z0 - 1, v);
+        load_fill(z0, w);
+        __syncthreads();
+        store_fill(z0 - 1, v);
+        store_fill(z0, w);
+        load_fill(z0 + 1, v);
+        __syncthreads();
+        store_phi(z0 + 2, load_phi(z0 + 2));
+        store_phi(z0 + 3, load_phi(z0 + 3));
+        __syncthreads();
+        store_fill(z0 + 1, v);
+        load_inputs(z0);
+        __syncthreads();
+    }
+
+    const int cown = (ty + 1) * kRlW + tx + 1;
+    for (int z = z0; z < z1; ++z) {
+        const bool fill = z + 2 <= z1;   // plane z+2 is needed (by node z+1)
+        const bool ring = z + 3 <= z1;   // phi plane z+4 is needed (for plane z+3)
+        double v[2][kRlPer], fp = 0.0;
+        if (fill) load_fill(z + 2, v);
+        if (ring) fp = load_phi(z + 4);
+        __builtin_amdgcn_sched_barrier(0);
+
+        // component c's stencil at node z: mu_c and rho~_c of planes z-1, z, z+1
+        const int bm = mod3(z - 1), b0 = mod3(z), bp = mod3(z + 1);
+        auto buf = [&](int dz) { return dz < 0 ? bm : (dz > 0 ? bp : b0); };
+        double gmu[3], grt[3];
+        double rc;
+        {
+            auto mu = [&](int dz) {
+                return [&, dz](int dx, int dy) { return s_f[buf(dz)][c][cown + dy * kRlW + dx]; };
+            };
+            auto r = [&](int dz) {
+                return [&, dz](int dx, int dy) { return s_f[buf(dz)][NC + c][cown + dy * kRlW + dx]; };
+            };
+            const IsoCross mdn = iso_cross(mu(-1)), mup = iso_cross(mu(1));
+            const IsoOwn mown = iso_own(mu(0));
+            iso_grad(mown.sx + mdn.ax, mown.sy + mdn.ay, mdn.b, mup, gmu);
+            const IsoCross rdn = iso_cross(r(-1)), rup = iso_cross(r(1));
+            const IsoOwn rown = iso_own(r(0));
+            iso_grad(rown.sx + rdn.ax, rown.sy + rdn.ay, rdn.b, rup, grt);
+            rc = rown.c;
+        }
+        double f[3];
+        P F[3], G[3];
+        comp_force<P>(kp, c, gmu, grt, rc, f, F, G);
+        // component c's density and momentum
+        double rho, mov, jc[3];
+        comp_density<L, P>(gv, ref, rho, mov);
+        comp_momentum<L, P>(gv, jc);
+        s_x[c][0][t] = rho;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_x[c][1 + k][t] = jc[k];
+            s_x[c][4 + k][t] = f[k];
+        }
+        __syncthreads();  // stencil reads of plane z-1's buffer done; exchange visible
+
+        if (fill) store_fill(z + 2, v);
+        if (ring) store_phi(z + 4, fp);
+        // totals in component order (as collide_push_loaded sums them)
+        double rtot = 0.0, j[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            rtot += s_x[i][0][t];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                j[k] += s_x[i][1 + k][t];
+                Fs[k] += s_x[i][4 + k][t];
+            }
+        }
+        double u[3];
+        node_velocity<3, P>(kp, rtot, j, Fs, fprev, u);
+        const int n = col + z * plane;
+        P oc[Q];
+        collide_comp<L, P, MRT>(kp, gv, rho, mov, u, F, G, oc);
+        push_comp<L, NC, P>(PushGeom<3, NC, P>(dm, n, x, y, z), gn, c, N, oc, nt != 0);
+        if (c == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st(fsum_out, ((unsigned)n * 3 + k) * (unsigned)sizeof(P), (P)Fs[k]);
+        }
+        if (z + 1 < z1) load_inputs(z + 1);
+        __syncthreads();  // fills of planes z+2 / z+4 visible; exchange free
     }
 }
 
@@ -1253,6 +1558,9 @@ static inline int xcd_chunk_for(const LaunchCfg& lc, int nblocks) {
 
 static inline dim3 grid_remapped(int nblocks, int chunk) { return dim3(chunk > 0 ? 8 * chunk : nblocks); }
 
+// Blocks of a z-marching launch in XCD y-band order (zmarch_tile_of_block).
+static inline int zmarch_grid(int tiles_x, int tiles_y, int nzc) { return 8 * ((tiles_y + 7) / 8) * tiles_x * nzc; }
+
 // Planes per slab of the visiting order (slab_order): one slab per XCD on a
 // D3Q19 lattice when enabled, 0 (plain order) otherwise.
 static inline int slab_planes(const LaunchCfg& lc, const KParams& kp) {
@@ -1351,18 +1659,32 @@ hipError_t launch_collide_zmarch_iso(const LaunchCfg& lc, const KParams& kp, con
                                      const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                      void* fsum_out) {
     if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1) return hipErrorInvalidValue;
-    const int nb = (kp.nx / kZX) * (kp.ny / kZY) * ((kp.nz + lc.zlen - 1) / lc.zlen);
+    const int tx = kp.nx / kZX, ty = kp.ny / kZY, nzc = (kp.nz + lc.zlen - 1) / lc.zlen;
+    const int nb = tx * ty * nzc;
     const int ch = xcd_chunk_for(lc, nb);
     const int nt = lc.nt_store ? 1 : 0;
+    const int zorder = lc.zorder;
+    const dim3 grid = zorder == 1 ? dim3(zmarch_grid(tx, ty, nzc)) : grid_remapped(nb, ch);
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
+        if constexpr (LAT == 1 && NC == 3) {
+            if (lc.csplit) {  // one component per 256-thread group
+                if (lc.mrt)
+                    k_collide_zmarch_iso_cs<NC, P, true><<<grid, 256 * NC, 0, lc.stream>>>(
+                        kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt, zorder);
+                else
+                    k_collide_zmarch_iso_cs<NC, P, false><<<grid, 256 * NC, 0, lc.stream>>>(
+                        kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt, zorder);
+                return;
+            }
+        }
         if constexpr (LAT == 1 && NC <= 3) {
             if (lc.mrt)
-                k_collide_zmarch_iso<NC, P, true><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
-                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+                k_collide_zmarch_iso<NC, P, true><<<grid, 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt, zorder);
             else
-                k_collide_zmarch_iso<NC, P, false><<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(
-                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt);
+                k_collide_zmarch_iso<NC, P, false><<<grid, 256, 0, lc.stream>>>(
+                    kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in, (P*)fsum_out, lc.zlen, ch, nt, zorder);
         }
     });
     return hipGetLastError();

@@ -70,10 +70,10 @@ def test_band_order_bitwise(wname, shape, precision, stencil, tune):
 def test_tuning_rejects_unknown_keys_and_values():
     w = wl.WORKLOADS["binary_slab_3d"].scaled((16, 8, 4))
     s = F.Solver(F.Params.from_workload(w, precision="fp32"))
-    for bad in ("bands=12", "k2block=100", "nosuchkey=1", "zmarch=2", "bands", "bands=8x"):
+    for bad in ("bands=12", "k2block=100", "nosuchkey=1", "zmarch=2", "csplit=3", "zorder=2", "bands", "bands=8x"):
         with pytest.raises(F.FLError) as ei:
             s.set_tuning(bad)
         assert ei.value.status == F.FL_EINVAL
-    s.set_tuning("bands=8, k2block=64".replace(" ", ""))
+    s.set_tuning("bands=8, k2block=64, csplit=0, zorder=1".replace(" ", ""))
     s.set_tuning(None)
     s.close()

@@ -152,29 +152,45 @@ ISO_CASES = [
     ("ternary_droplets_3d", (64, 12, 16), "fp32", "MRT", 16),
     ("ternary_droplets_3d", (128, 8, 11), "fp32", "MRT", 4),   # ragged last z-range, two tiles in x
     ("ternary_droplets_3d", (64, 8, 7), "fp64", "MRT", 3),
+    ("ternary_droplets_3d", (64, 52, 6), "fp32", "MRT", 4),    # 13 tile rows: unequal XCD y-bands
+    ("ternary_droplets_3d", (256, 12, 9), "fp32", "MRT", 4),   # four tiles in x, ragged z-range
     ("binary_slab_3d", (64, 8, 9), "fp32", "BGK", 2),
     ("binary_slab_3d", (64, 4, 1), "fp64", "BGK", 16),         # one plane: z -+ 1 wrap onto itself
     ("binary_slab_3d", (64, 4, 2), "fp32", "MRT", 1),          # two planes, one per workgroup
 ]
 
 
+def iso_zmarch_name(ncomp, csplit):
+    """The z-marching isotropic collide kernel a step runs: with three
+    components each component gets its own 256 threads unless csplit=0."""
+    return "k_collide_zmarch_iso_cs" if ncomp == 3 and csplit else "k_collide_zmarch_iso"
+
+
+@pytest.mark.parametrize("csplit,zorder", [(1, 0), (1, 1), (0, 0), (0, 1)])
 @pytest.mark.parametrize("wname,shape,precision,coll,zlen", ISO_CASES)
-def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zlen):
+def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zlen, csplit, zorder):
     """The z-marching kernel with the isotropic stencils (which forms
     -lap(phi) and mu_i in LDS as planes pass) against the one-thread-per-node
     kernel after the Laplacian pass: the same per-node expressions, so the
-    same bits, on a droplet that varies along every axis."""
+    same bits, on a droplet that varies along every axis.  With three
+    components, both forms of the z-marching kernel: one thread per node
+    (csplit=0) and one 256-thread group per component exchanging densities,
+    momenta and forces through LDS (csplit=1); each in both block orders
+    (zorder 0: XCD-contiguous chunks, 1: XCD y-bands)."""
     w = wl.WORKLOADS[wname].scaled(shape)
+    if w.ncomp != 3 and csplit == 0:
+        pytest.skip("csplit applies to three components only")
     w.collision = coll
-    announce(f"iso zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen}")
+    announce(f"iso zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen} csplit={csplit} "
+             f"zorder={zorder}")
     rho = _sphere(w, shape, 0.3 * min(shape[:2]) if shape[2] > 2 else 1.5)
     p = F.Params.from_workload(w, precision=precision, stencil="isotropic")
     a, b = F.Solver(p), F.Solver(p)
-    a.set_tuning(f"zmarch=1,zlen={zlen}")
+    a.set_tuning(f"zmarch=1,zlen={zlen},csplit={csplit},zorder={zorder}")
     b.set_tuning("zmarch=0")
     a.set_state(rho)
     b.set_state(rho)
-    assert list(a.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch_iso"]
+    assert list(a.step_timed(1)) == ["k_moments_eos", iso_zmarch_name(w.ncomp, csplit)]
     assert set(b.step_timed(1)) == {"k_moments_eos", "k_collide_stream", "k_interface_lap"}
     a.step(14)
     b.step(14)
@@ -186,21 +202,22 @@ def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zl
     b.close()
 
 
-def test_zmarch_isotropic_fp64_vs_oracle():
-    """FP64 z-marching isotropic kernel against the oracle's isotropic form on
-    a ternary sphere (MRT), element by element (1e-12)."""
+@pytest.mark.parametrize("csplit", [0, 1])
+def test_zmarch_isotropic_fp64_vs_oracle(csplit):
+    """FP64 z-marching isotropic kernel (both forms) against the oracle's
+    isotropic form on a ternary sphere (MRT), element by element (1e-12)."""
     shape = (64, 12, 10)
     w = wl.WORKLOADS["ternary_droplets_3d"].scaled(shape)
-    announce(f"iso zmarch FP64 vs oracle {shape}")
+    announce(f"iso zmarch FP64 vs oracle {shape} csplit={csplit}")
     rho = _sphere(w, shape, 4.0).reshape(3, -1)
     o = oracle_for(w, stencil="isotropic")
     o.init(rho)
     s = F.Solver(F.Params.from_workload(w, precision="fp64", stencil="isotropic"))
     # three components in FP64 default to the three-pass form; the z-marching
     # kernel is asked for
-    s.set_tuning("zmarch=1")
+    s.set_tuning(f"zmarch=1,csplit={csplit}")
     s.set_state(rho)
-    assert list(s.step_timed(1)) == ["k_moments_eos", "k_collide_zmarch_iso"]
+    assert list(s.step_timed(1)) == ["k_moments_eos", iso_zmarch_name(3, csplit)]
     o.run(1)
     s.step(29)
     o.run(29)
@@ -213,13 +230,14 @@ def test_zmarch_isotropic_fp64_vs_oracle():
 
 def test_bench_lattice_isotropic_zmarch_equals_plain():
     """The 256^3 ternary two-droplet lattice of the benchmark (FP32, MRT,
-    isotropic stencils): z-marching and one-thread-per-node kernels bitwise
-    equal after three steps."""
+    isotropic stencils): both z-marching forms and the one-thread-per-node
+    kernel bitwise equal after three steps."""
     w = wl.WORKLOADS["ternary_droplets_3d"]
     announce(f"bench lattice isotropic {w.shape}")
     rho, u = wl.initial_field(w)
     out = []
-    for tune in ("zmarch=1", "zmarch=0"):
+    for tune in ("zmarch=1", "zmarch=1,csplit=0", "zmarch=0", "zmarch=1,zorder=1,zlen=8",
+                 "zmarch=1,csplit=0,zorder=1,zlen=4", "zmarch=1,zorder=0"):
         s = F.Solver(F.Params.from_workload(w, precision="fp32", stencil="isotropic"))
         s.set_tuning(tune)
         s.set_state(rho, u)
@@ -227,4 +245,5 @@ def test_bench_lattice_isotropic_zmarch_equals_plain():
         out.append(s.fields()["rho_molar"])
         s.close()
         del s
-    assert np.array_equal(out[0], out[1])
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)

@@ -109,3 +109,50 @@ def test_band_order_sweeps_z_inside_a_band():
     assert list(z[:2 * nz]) == [0, 0, 1, 1, 2, 2]
     assert set(y[:2 * nz]) == {0, 1}
     assert set(y[2 * nz:]) == {16, 17}                # band 8 = XCD 0's second band
+
+
+def zmarch_tile_of_block(b, tiles_x, tiles_y, nzc, xcd_chunk, zorder):
+    """The z-marching kernels' block -> (z-range, tile) map, replayed with their
+    integer arithmetic; (-1, -1) for an idle block."""
+    if zorder == 1:
+        k, j = b & 7, b >> 3
+        rows = (tiles_y + 7) >> 3
+        per = rows * tiles_x
+        zc = j // per
+        tl = j - zc * per
+        r0, r1 = (k * tiles_y) >> 3, ((k + 1) * tiles_y) >> 3
+        ty = r0 + tl // tiles_x
+        ok = (zc < nzc) & (ty < r1)
+        txy = ty * tiles_x + tl % tiles_x
+    else:
+        lb = (b & 7) * xcd_chunk + (b >> 3) if xcd_chunk > 0 else b
+        zc = lb // (tiles_x * tiles_y)
+        txy = lb - zc * tiles_x * tiles_y
+        ok = lb < tiles_x * tiles_y * nzc
+    return np.where(ok, zc, -1), np.where(ok, txy, -1)
+
+
+@pytest.mark.parametrize("tiles_x,tiles_y,nzc", [(4, 64, 16), (1, 1, 1), (2, 3, 5), (1, 8, 2), (3, 13, 4),
+                                                 (4, 64, 64), (1, 17, 3)])
+@pytest.mark.parametrize("zorder", [0, 1])
+def test_zmarch_block_order_is_a_bijection(tiles_x, tiles_y, nzc, zorder):
+    """Every (z-range, tile) pair of a z-marching launch is taken by exactly
+    one block, in the XCD-contiguous and in the XCD y-band order (bands of
+    unequal height when the tile rows are not a multiple of 8); in the y-band
+    order the blocks of XCD k (b % 8 == k) stay inside band k and take the
+    z-ranges in order."""
+    nb = tiles_x * tiles_y * nzc
+    chunk = (nb + 7) // 8
+    grid = 8 * ((tiles_y + 7) // 8) * tiles_x * nzc if zorder == 1 else 8 * chunk
+    b = np.arange(grid)
+    zc, txy = zmarch_tile_of_block(b, tiles_x, tiles_y, nzc, chunk, zorder)
+    ok = zc >= 0
+    key = zc[ok] * tiles_x * tiles_y + txy[ok]
+    assert key.size == nb
+    assert np.array_equal(np.sort(key), np.arange(nb))
+    if zorder == 1:
+        for k in range(8):
+            sel = ok & (b % 8 == k)
+            ty = txy[sel] // tiles_x
+            assert np.all((ty >= (k * tiles_y) // 8) & (ty < ((k + 1) * tiles_y) // 8))
+            assert np.all(np.diff(zc[sel]) >= 0)
