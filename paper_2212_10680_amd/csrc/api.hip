@@ -208,12 +208,15 @@ void default_launch(fl_solver* s) {
         lc.block_k2 = 64;
         lc.xcd_remap_k2 = true;
         // The z-marching form there gives each component its own 256 threads
-        // (three waves per SIMD instead of one; the same time, 2.51 ms on the
-        // 256^3 ternary lattice either way) and takes its workgroups in XCD
-        // y-bands, so that all XCDs march through the same planes at once:
-        // 2.60 -> 2.51 ms against XCD-contiguous chunks.
+        // (three waves per SIMD instead of one: the same time, 2.51 ms on the
+        // 256^3 ternary lattice, with its fills where the other form has them;
+        // 2.34 ms with the fills after the pushes), takes its workgroups in
+        // XCD y-bands, so that all XCDs march through the same planes at once
+        // (2.60 -> 2.51 ms against XCD-contiguous chunks), and runs 32 planes
+        // per workgroup (2.34 -> 2.31 ms; 24 planes 2.33).
         lc.csplit = true;
         lc.zorder = 1;
+        lc.zlen = 32;
     }
 }
 

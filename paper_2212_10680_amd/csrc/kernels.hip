@@ -1306,8 +1306,6 @@ __global__ __launch_bounds__(256 * NC) void k_collide_zmarch_iso_cs(
         }
         __syncthreads();  // stencil reads of plane z-1's buffer done; exchange visible
 
-        if (fill) store_fill(z + 2, v);
-        if (ring) store_phi(z + 4, fp);
         // totals in component order (as collide_push_loaded sums them)
         double rtot = 0.0, j[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1330,6 +1328,10 @@ __global__ __launch_bounds__(256 * NC) void k_collide_zmarch_iso_cs(
             for (int k = 0; k < 3; ++k) st(fsum_out, ((unsigned)n * 3 + k) * (unsigned)sizeof(P), (P)Fs[k]);
         }
         if (z + 1 < z1) load_inputs(z + 1);
+        // the plane fills after the pushes and the next plane's loads: the
+        // stores drain and the loads arrive while the Laplacians are formed
+        if (fill) store_fill(z + 2, v);
+        if (ring) store_phi(z + 4, fp);
         __syncthreads();  // fills of planes z+2 / z+4 visible; exchange free
     }
 }
