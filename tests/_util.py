@@ -92,20 +92,48 @@ def central_pairs(rho):
     return rho[:, pair(idx[liquid])].mean(axis=1), rho[:, pair(idx[~liquid])].mean(axis=1)
 
 
+def flash_bulk_pairs(mix, z, rho_L, rho_V, names=("C3", "C5")):
+    """Bulk density and mole fractions of each phase with their references
+    from a PT flash of the feed z at the liquid bulk's EOS pressure:
+    {phase: {"density" | "x_<name>": (value, flash value)}}."""
+    fr = th.flash(mix, z, mix.pressure(rho_L))
+    assert fr.two_phase
+    out = {}
+    for phase, r, v, comp in (("liquid", rho_L, fr.vL, fr.x), ("vapor", rho_V, fr.vV, fr.y)):
+        d = {"density": (r.sum(), 1.0 / v)}
+        for i, n in enumerate(names):
+            d["x_" + n] = (r[i] / r.sum(), comp[i])
+        out[phase] = d
+    return out
+
+
+def flash_agreement(mix, z, row_a, row_b, names=("C3", "C5")):
+    """How the flash errors of two flat-interface states (rows [nc, n]) compare:
+    (dq, dref, derr, bound) with dq the largest relative difference of their
+    bulk values, dref that of their flash references (each flash is taken at
+    its state's own bulk pressure), derr the largest difference of the errors
+    (percentage points) and bound its triangle-inequality bound, the largest
+    100 (|q - q'| / q_f + q' |q_f - q_f'| / (q_f q_f')).  The errors of the two
+    states are equal to within what dq and dref allow when derr <= bound."""
+    pa = flash_bulk_pairs(mix, z, *bulk_values(row_a), names)
+    pb = flash_bulk_pairs(mix, z, *bulk_values(row_b), names)
+    dq = dref = derr = bound = 0.0
+    for ph in pa:
+        for k, (q, qf) in pa[ph].items():
+            qb, qfb = pb[ph][k]
+            dq = max(dq, abs(q - qb) / abs(qb))
+            dref = max(dref, abs(qf - qfb) / abs(qfb))
+            derr = max(derr, abs(100.0 * abs(q - qf) / qf - 100.0 * abs(qb - qfb) / qfb))
+            bound = max(bound, 100.0 * (abs(q - qb) / qf + qb * abs(qf - qfb) / (qf * qfb)))
+    return dq, dref, derr, bound
+
+
 def flash_errors_percent(mix, z, rho_L, rho_V, names=("C3", "C5")):
     """Relative errors (eq. eqerror, in %) of bulk density and mole fractions
     against a PT flash of the feed z at the liquid bulk's EOS pressure.
     Keys: "density" and "x_<name>" per component."""
-    fr = th.flash(mix, z, mix.pressure(rho_L))
-    assert fr.two_phase
-    err = lambda a, b: 100.0 * abs(a - b) / b
-    out = {}
-    for phase, r, v, comp in (("liquid", rho_L, fr.vL, fr.x), ("vapor", rho_V, fr.vV, fr.y)):
-        d = {"density": err(r.sum(), 1.0 / v)}
-        for i, n in enumerate(names):
-            d["x_" + n] = err(r[i] / r.sum(), comp[i])
-        out[phase] = d
-    return out
+    pairs = flash_bulk_pairs(mix, z, rho_L, rho_V, names)
+    return {ph: {k: 100.0 * abs(q - qf) / qf for k, (q, qf) in d.items()} for ph, d in pairs.items()}
 
 
 def half_width(line, centre, level):
