@@ -237,7 +237,7 @@ def test_bench_lattice_isotropic_zmarch_equals_plain():
     rho, u = wl.initial_field(w)
     out = []
     for tune in ("zmarch=1", "zmarch=1,csplit=0", "zmarch=0", "zmarch=1,zorder=1,zlen=8",
-                 "zmarch=1,csplit=0,zorder=1,zlen=4", "zmarch=1,zorder=0"):
+                 "zmarch=1,csplit=0,zorder=1,zlen=4", "zmarch=1,zorder=0", "zmarch=1,remap=1,k1block=128"):
         s = F.Solver(F.Params.from_workload(w, precision="fp32", stencil="isotropic"))
         s.set_tuning(tune)
         s.set_state(rho, u)
