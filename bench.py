@@ -489,6 +489,10 @@ def main():
         buf = ctypes.create_string_buffer(1 << 14)
         rc = lib.flp_stream_probe(buf, len(buf))
         print(buf.value.decode(), end="")
+        if rc == 0:
+            buf = ctypes.create_string_buffer(1 << 14)
+            rc = lib.flp_zmarch_probe(buf, len(buf))
+            print(buf.value.decode(), end="")
         sys.exit(0 if rc == 0 else 1)
     F.load()  # fails loudly when the HIP library is not built
 

@@ -66,9 +66,129 @@ __global__ void k_copy(const float4* a, float4* b, long n4) {
     if (i < n4) b[i] = a[i];
 }
 
+// ---- visiting orders of the three-component collide pass (256^3 lattice,
+// 57 population streams of 4 B in and out, push-shifted destinations, no
+// arithmetic and no stencil fields): one thread per node in node order, or
+// z-marching workgroups of 256 threads that own a tile of the (x, y) plane and
+// march 16 planes, taken in XCD-contiguous chunks or in XCD y-bands (all XCDs
+// in the same planes).  LDS padding holds one workgroup per CU, as in the
+// collide kernel.  Each thread loads all its streams before it stores.
+constexpr int kMX = 256, kMY = 256, kMZ = 256;
+constexpr int kMN = kMX * kMY * kMZ;
+constexpr int kMS = 57;
+struct MStreams {
+    float* p[kMS];
+};
+__constant__ int c_ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ int c_ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ int c_ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__device__ __forceinline__ int mlin(int x, int y, int z) { return x + kMX * (y + kMY * z); }
+
+// ORDER 0: node order, one node per thread; 1: z-march, XCD-contiguous chunks;
+// 2: z-march, XCD y-bands.  TW: tile width (tile height 256 / TW).  XSHIFT:
+// destinations shifted along x too (false: y and z only).
+template <int ORDER, int TW, bool XSHIFT>
+__global__ __launch_bounds__(256) void k_zorder(MStreams in, MStreams out) {
+    __shared__ float pad[24 * 1024];  // 96 KB: one workgroup per CU
+    if (threadIdx.x == 1023) pad[blockIdx.x & 1023] = 0.f;  // never taken: keeps the array
+    const int t = threadIdx.x;
+    auto node = [&](int x, int y, int z) {
+        float v[kMS];
+        const int n = mlin(x, y, z);
+#pragma unroll
+        for (int s = 0; s < kMS; ++s) v[s] = __builtin_nontemporal_load(&in.p[s][n]);
+#pragma unroll
+        for (int s = 0; s < kMS; ++s) {
+            const int a = s % 19;
+            const int xx = XSHIFT ? (x + c_ex[a]) & (kMX - 1) : x;
+            out.p[s][mlin(xx, (y + c_ey[a]) & (kMY - 1), (z + c_ez[a]) & (kMZ - 1))] = v[s] * 1.0001f;
+        }
+    };
+    if (ORDER == 0) {
+        const int n = blockIdx.x * 256 + t;
+        node(n & (kMX - 1), (n / kMX) & (kMY - 1), n / (kMX * kMY));
+        return;
+    }
+    constexpr int TH = 256 / TW, TX = kMX / TW, TY = kMY / TH, ZL = 16;
+    constexpr int tiles = TX * TY, nb = tiles * (kMZ / ZL);
+    const int b = blockIdx.x;
+    int zc, txy;
+    if (ORDER == 1) {
+        const int lb = (b & 7) * (nb / 8) + (b >> 3);
+        zc = lb / tiles;
+        txy = lb % tiles;
+    } else {
+        const int k = b & 7, j = b >> 3, per = tiles / 8;
+        zc = j / per;
+        const int tl = j % per;
+        txy = (k * (per / TX) + tl / TX) * TX + tl % TX;
+    }
+    const int x = (txy % TX) * TW + t % TW, y = (txy / TX) * TH + t / TW;
+    for (int z = zc * ZL; z < zc * ZL + ZL; ++z) node(x, y, z);
+}
+
 }  // namespace
 
 extern "C" {
+
+// Runs each visiting order of k_zorder (10 launches, HIP events) and writes
+// one line per order into `report` (at most `cap` bytes, NUL-terminated).
+// Returns 0, or -1 on a HIP error (the report names it).  Allocates 7.7 GB.
+int flp_zmarch_probe(char* report, int cap) {
+    int used = 0;
+    auto put = [&](const char* fmt, auto... a) {
+        if (used < cap) used += snprintf(report + used, (size_t)(cap - used), fmt, a...);
+    };
+    MStreams in{}, out{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    auto ck = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == 0) {
+            put("HIP error %s in %s\n", hipGetErrorString(e), what);
+            rc = -1;
+        }
+        return rc == 0;
+    };
+    for (int s = 0; s < kMS && rc == 0; ++s) {
+        ck(hipMalloc(&in.p[s], (size_t)kMN * 4), "hipMalloc");
+        if (rc == 0) ck(hipMalloc(&out.p[s], (size_t)kMN * 4), "hipMalloc");
+        if (rc == 0) ck(hipMemset(in.p[s], 0, (size_t)kMN * 4), "hipMemset");
+    }
+    if (rc == 0) ck(hipEventCreate(&e0), "hipEventCreate");
+    if (rc == 0) ck(hipEventCreate(&e1), "hipEventCreate");
+    auto run = [&](const char* name, auto launch) {
+        if (rc) return;
+        launch();
+        if (!ck(hipDeviceSynchronize(), name)) return;
+        ck(hipEventRecord(e0), name);
+        for (int r = 0; r < 10; ++r) launch();
+        ck(hipEventRecord(e1), name);
+        if (!ck(hipEventSynchronize(e1), name)) return;
+        float ms = 0.f;
+        ck(hipEventElapsedTime(&ms, e0, e1), name);
+        ms /= 10.f;
+        const double bytes = 2.0 * kMS * 4.0 * kMN;
+        put("%-58s %8.3f ms %6.0f GB/s\n", name, ms, bytes / (ms * 1e-3) / 1e9);
+    };
+    const int nz = (kMX / 64) * (kMY / 4) * (kMZ / 16);
+    run("57 x 4 B push-shifted, node order", [&] { k_zorder<0, 64, true><<<kMN / 256, 256>>>(in, out); });
+    run("57 x 4 B push-shifted, z-march 64x4, XCD chunks", [&] { k_zorder<1, 64, true><<<nz, 256>>>(in, out); });
+    run("57 x 4 B push-shifted, z-march 64x4, XCD y-bands", [&] { k_zorder<2, 64, true><<<nz, 256>>>(in, out); });
+    run("57 x 4 B shifted in y, z only, z-march 64x4, XCD y-bands",
+        [&] { k_zorder<2, 64, false><<<nz, 256>>>(in, out); });
+    run("57 x 4 B push-shifted, z-march 128x2, XCD y-bands", [&] { k_zorder<2, 128, true><<<nz, 256>>>(in, out); });
+    run("57 x 4 B push-shifted, z-march 256x1 (whole rows), XCD y-bands",
+        [&] { k_zorder<2, 256, true><<<nz, 256>>>(in, out); });
+    for (int s = 0; s < kMS; ++s) {
+        if (in.p[s]) (void)hipFree(in.p[s]);
+        if (out.p[s]) (void)hipFree(out.p[s]);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
 
 // Runs every pattern (10 launches each, HIP events) and writes one line per
 // pattern into `report` (at most `cap` bytes, NUL-terminated).  Returns 0, or
