@@ -97,8 +97,7 @@ typedef struct fl_component {
  *               stable for 3-D droplets, where the axis ones are not.  With
  *               them a step is the moments pass and a z-marching collide pass
  *               that computes -lap(phi) itself where it fits (D3Q19, N_c <= 3,
- *               nx % 64 == 0, ny % 4 == 0; by default not with N_c = 3 in
- *               FP64, where the three-pass form is faster), otherwise three
+ *               nx % 64 == 0, ny % 4 == 0), otherwise three
  *               passes (moments, -lap(phi) at every node, one-thread-per-node
  *               collide); never
  *               the one-launch form; fl_required_bytes counts one more FP64
@@ -165,9 +164,9 @@ int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_
  * reverse order), order (y-major rows inside per-XCD z-slabs), csplit (with
  * the isotropic stencils and N_c = 3: the z-marching collide pass gives each
  * component its own 256 threads, 1 by default; 0 keeps a node in one thread),
- * zorder (block order of the isotropic z-marching pass: 0 XCD-contiguous
+ * zorder (block order of the z-marching collide passes: 0 XCD-contiguous
  * chunks, 1 XCD y-bands, all XCDs marching through the same planes; 1 by
- * default with N_c >= 3), zlen (planes per z-marching workgroup, 1..4096), bands and lapbands (XCD-band order of
+ * default with the isotropic stencils and N_c >= 3), zlen (planes per z-marching workgroup, 1..4096), bands and lapbands (XCD-band order of
  * the plain collide pass and of the interface-Laplacian pass: the rows of each
  * plane cut into that many bands, a multiple of 8, each XCD sweeping its bands
  * along z; 0 = off).  FL_EINVAL (tuning unchanged) for an

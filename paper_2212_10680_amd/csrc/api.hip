@@ -186,11 +186,8 @@ void default_launch(fl_solver* s) {
     // its registers cost more than the re-reads it saves (measured on the
     // 256^3 ternary lattice).  With the isotropic stencils the plain kernel's
     // 18-neighbour gathers of seven FP64 fields set its time, and the
-    // z-marching form (which also computes -lap(phi) itself) is used, except
-    // with three or more components in FP64, where its collision spills
-    // (256^3 ternary: 6.59 ms against 4.58 + 0.21 ms for the plain kernel and
-    // the Laplacian pass).
-    lc.zmarch = p.ncomp <= 2 || (p.stencil == FL_STENCIL_ISOTROPIC && p.precision != FL_FP64);
+    // z-marching form (which also computes -lap(phi) itself) is used.
+    lc.zmarch = p.ncomp <= 2 || p.stencil == FL_STENCIL_ISOTROPIC;
     // Plain collide kernel block size: 128 threads with the interleaved layout
     // (N_c <= 2), 256 with the component-major one, whose N_c * Q streams of
     // 4 B per node read and write in longer runs per block (measured:
@@ -214,7 +211,10 @@ void default_launch(fl_solver* s) {
         // XCD y-bands, so that all XCDs march through the same planes at once
         // (2.60 -> 2.51 ms against XCD-contiguous chunks), and runs 32 planes
         // per workgroup (2.34 -> 2.31 ms; 24 planes 2.33).
-        lc.csplit = true;
+        // In FP64 the split form spills (9.87 ms per step against 6.42 for the
+        // plain collide kernel and the Laplacian pass), and the one-thread-per-
+        // node z-march in this order takes 6.19 ms.
+        lc.csplit = p.precision != FL_FP64;
         lc.zorder = 1;
         lc.zlen = 32;
         // The moments pass (no stencil, so nothing for an XCD's L2 to keep)

@@ -781,6 +781,37 @@ constexpr int kRlPer = (kRlPts + 255) / 256;
 template <int NC, typename P>
 constexpr int kZmarchWaves = (sizeof(P) == 4 && NC <= 2) ? 2 : 1;
 
+// The tile (txy) and z-range (zc) of z-marching workgroup b, or false for a
+// workgroup with no work.  Hardware block b runs on XCD b % 8.
+//   zorder 0: XCD-contiguous chunks: XCD k takes the logical blocks
+//             k * xcd_chunk .. (k + 1) * xcd_chunk - 1 (tiles fastest, then
+//             z-ranges; xcd_chunk = 0: logical block b);
+//   zorder 1: XCD y-bands: the tile rows are cut into 8 bands of at most
+//             ceil(tiles_y / 8) rows, XCD k takes band k of every z-range,
+//             z-ranges in order, so that all XCDs march through the same planes
+//             at once (the DRAM pages of every stream then open for one window
+//             of addresses instead of eight) and a band's halo planes, read
+//             again by its next z-range, stay in its XCD's L2.  The grid is
+//             zmarch_grid() blocks; a shorter band leaves blocks idle.
+__device__ __forceinline__ bool zmarch_tile_of_block(int b, int tiles_x, int tiles_y, int nzc, int xcd_chunk,
+                                                     int zorder, int& zc, int& txy) {
+    if (zorder == 1) {
+        const int k = b & 7, j = b >> 3;
+        const int rows = (tiles_y + 7) >> 3;           // tile rows per band, at most
+        const int per = rows * tiles_x;                 // blocks per band and z-range
+        zc = j / per;
+        const int tl = j - zc * per;
+        const int r0 = (k * tiles_y) >> 3, r1 = ((k + 1) * tiles_y) >> 3;
+        const int ty = r0 + tl / tiles_x;
+        txy = ty * tiles_x + tl % tiles_x;
+        return zc < nzc && ty < r1;
+    }
+    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
+    zc = lb / (tiles_x * tiles_y);
+    txy = lb - zc * tiles_x * tiles_y;
+    return lb < tiles_x * tiles_y * nzc;
+}
+
 template <int NC, typename P, bool MRT, int DIR>
 __global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(KParams kp, const P* __restrict__ g,
                                                         P* __restrict__ gn,
@@ -788,7 +819,7 @@ __global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(K
                                                         const double* __restrict__ rt,
                                                         const double* __restrict__ lnf,
                                                         const P* fsum_in, P* fsum_out, int zlen, int xcd_chunk,
-                                                        int nt) {
+                                                        int nt, int zorder) {
     // DIR = +1 marches each z-range upward, -1 downward (and takes an XCD's
     // z-ranges top-down), so that a pass following one sweep starts where that
     // sweep ended.  All ring bookkeeping is relative to the march direction:
@@ -801,10 +832,18 @@ __global__ __launch_bounds__(256, (kZmarchWaves<NC, P>)) void k_collide_zmarch(K
     const int tiles_xy = tiles_x * (ny / kZY);
     const int nzc = (nz + zlen - 1) / zlen;
     const int b = blockIdx.x;
-    const int j = b >> 3;
-    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (DIR > 0 ? j : xcd_chunk - 1 - j) : b;
-    if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
-    const int zc = lb / tiles_xy, txy = lb - zc * tiles_xy;
+    int zc, txy;
+    if (zorder == 1) {
+        // XCD y-bands (z-ranges top-down when marching downward)
+        if (!zmarch_tile_of_block(b, tiles_x, tiles_xy / tiles_x, nzc, 0, 1, zc, txy)) return;
+        if (DIR < 0) zc = nzc - 1 - zc;
+    } else {
+        const int j = b >> 3;
+        const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (DIR > 0 ? j : xcd_chunk - 1 - j) : b;
+        if (lb >= tiles_xy * nzc) return;  // whole workgroup, before any barrier
+        zc = lb / tiles_xy;
+        txy = lb - zc * tiles_xy;
+    }
     const int x0 = (txy % tiles_x) * kZX, y0 = (txy / tiles_x) * kZY;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, nz);
     const int start = DIR > 0 ? z0 : z1 - 1;
@@ -960,36 +999,6 @@ constexpr int kZmarchIsoWaves = (sizeof(P) == 4 && NC == 1) ? 2 : 1;
 
 __device__ __forceinline__ int mod3(int q) { return ((q % 3) + 3) % 3; }
 
-// The tile (txy) and z-range (zc) of z-marching workgroup b, or false for a
-// workgroup with no work.  Hardware block b runs on XCD b % 8.
-//   zorder 0: XCD-contiguous chunks: XCD k takes the logical blocks
-//             k * xcd_chunk .. (k + 1) * xcd_chunk - 1 (tiles fastest, then
-//             z-ranges; xcd_chunk = 0: logical block b);
-//   zorder 1: XCD y-bands: the tile rows are cut into 8 bands of at most
-//             ceil(tiles_y / 8) rows, XCD k takes band k of every z-range,
-//             z-ranges in order, so that all XCDs march through the same planes
-//             at once (the DRAM pages of every stream then open for one window
-//             of addresses instead of eight) and a band's halo planes, read
-//             again by its next z-range, stay in its XCD's L2.  The grid is
-//             zmarch_grid() blocks; a shorter band leaves blocks idle.
-__device__ __forceinline__ bool zmarch_tile_of_block(int b, int tiles_x, int tiles_y, int nzc, int xcd_chunk,
-                                                     int zorder, int& zc, int& txy) {
-    if (zorder == 1) {
-        const int k = b & 7, j = b >> 3;
-        const int rows = (tiles_y + 7) >> 3;           // tile rows per band, at most
-        const int per = rows * tiles_x;                 // blocks per band and z-range
-        zc = j / per;
-        const int tl = j - zc * per;
-        const int r0 = (k * tiles_y) >> 3, r1 = ((k + 1) * tiles_y) >> 3;
-        const int ty = r0 + tl / tiles_x;
-        txy = ty * tiles_x + tl % tiles_x;
-        return zc < nzc && ty < r1;
-    }
-    const int lb = xcd_chunk > 0 ? (b & 7) * xcd_chunk + (b >> 3) : b;
-    zc = lb / (tiles_x * tiles_y);
-    txy = lb - zc * tiles_x * tiles_y;
-    return lb < tiles_x * tiles_y * nzc;
-}
 
 template <int NC, typename P, bool MRT>
 __global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarch_iso(
@@ -1632,18 +1641,19 @@ hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const v
                                  const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                  void* fsum_out) {
     if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1) return hipErrorInvalidValue;
-    const int nb = (kp.nx / kZX) * (kp.ny / kZY) * ((kp.nz + lc.zlen - 1) / lc.zlen);
+    const int tx = kp.nx / kZX, ty = kp.ny / kZY, nzc = (kp.nz + lc.zlen - 1) / lc.zlen;
+    const int nb = tx * ty * nzc;
     const int ch = xcd_chunk_for(lc, nb);
     const int nt = lc.nt_store ? 1 : 0;
+    const dim3 grid = lc.zorder == 1 ? dim3(zmarch_grid(tx, ty, nzc)) : grid_remapped(nb, ch);
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
         if constexpr (LAT == 1 && NC <= 3) {
             // march downward when the passes alternate direction (reverse_k2)
             auto go = [&](auto mrt, auto dir) {
                 k_collide_zmarch<NC, P, decltype(mrt)::value, decltype(dir)::value>
-                    <<<grid_remapped(nb, ch), 256, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf,
-                                                                   (const P*)fsum_in, (P*)fsum_out, lc.zlen,
-                                                                   ch, nt);
+                    <<<grid, 256, 0, lc.stream>>>(kp, (const P*)g, (P*)gn, rref, rt, lnf, (const P*)fsum_in,
+                                                  (P*)fsum_out, lc.zlen, ch, nt, lc.zorder);
             };
             using Up = std::integral_constant<int, 1>;
             using Down = std::integral_constant<int, -1>;

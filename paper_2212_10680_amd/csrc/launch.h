@@ -28,8 +28,8 @@ struct LaunchCfg {
     bool reverse_k2 = false;  // collide/stream sweeps the nodes last to first (set per solver)
     bool slab_order = false;  // y-major row order inside per-XCD z-slabs (fl_set_tuning "order=1")
     int zlen = 16;          // planes per workgroup of the z-marching kernel
-    int zorder = 0;         // block order of the isotropic z-marching kernels: 0 XCD-contiguous
-                            // chunks, 1 XCD y-bands (zmarch_tile_of_block)
+    int zorder = 0;         // block order of the z-marching kernels: 0 XCD-contiguous chunks,
+                            // 1 XCD y-bands (zmarch_tile_of_block)
     bool csplit = true;     // isotropic z-marching kernel with N_c = 3: one component per
                             // 256-thread group (fl_set_tuning "csplit=0": one thread per node)
     int bands = 0;          // XCD-band order of the plain collide pass (band_node): row bands, a

@@ -39,19 +39,21 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("zorder", [0, 1])
 @pytest.mark.parametrize("rev", [0, 1])
 @pytest.mark.parametrize("wname,shape,precision,coll,zlen", CASES)
-def test_zmarch_equals_plain_bitwise(wname, shape, precision, coll, zlen, rev):
+def test_zmarch_equals_plain_bitwise(wname, shape, precision, coll, zlen, rev, zorder):
     """rev = 1 marches each z-range downward (the default when the passes
-    alternate direction), rev = 0 upward."""
+    alternate direction), rev = 0 upward; zorder 0 takes the workgroups in
+    XCD-contiguous chunks, 1 in XCD y-bands."""
     w = wl.WORKLOADS[wname].scaled(shape)
     w.collision = coll
     w.u0 = 0.0
     if w.geometry == "two_droplets":
         w.geometry = "slab"
-    announce(f"zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen} rev={rev}")
+    announce(f"zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen} rev={rev} zorder={zorder}")
     rho, u = smooth_3d_field(w, amp=0.005)
-    a = solver(w, precision, f"zmarch=1,zlen={zlen},rev={rev}")
+    a = solver(w, precision, f"zmarch=1,zlen={zlen},rev={rev},zorder={zorder}")
     b = solver(w, precision, f"zmarch=0,rev={rev}")
     a.set_state(rho, u)
     b.set_state(rho, u)
@@ -213,8 +215,8 @@ def test_zmarch_isotropic_fp64_vs_oracle(csplit):
     o = oracle_for(w, stencil="isotropic")
     o.init(rho)
     s = F.Solver(F.Params.from_workload(w, precision="fp64", stencil="isotropic"))
-    # three components in FP64 default to the three-pass form; the z-marching
-    # kernel is asked for
+    # three components in FP64 default to the one-thread-per-node form; both
+    # are asked for
     s.set_tuning(f"zmarch=1,csplit={csplit}")
     s.set_state(rho)
     assert list(s.step_timed(1)) == ["k_moments_eos", iso_zmarch_name(3, csplit)]
