@@ -97,7 +97,7 @@ typedef struct fl_component {
  *               stable for 3-D droplets, where the axis ones are not.  With
  *               them a step is the moments pass and a z-marching collide pass
  *               that computes -lap(phi) itself where it fits (D3Q19, N_c <= 3,
- *               nx % 64 == 0, ny % 4 == 0), otherwise three
+ *               nx % 64 == 0, ny % 4 == 0, nz >= 2), otherwise three
  *               passes (moments, -lap(phi) at every node, one-thread-per-node
  *               collide); never
  *               the one-launch form; fl_required_bytes counts one more FP64

@@ -233,7 +233,8 @@ int xcd_placement_ok(hipStream_t stream);
 // Which kernels a step launches, from the launch choices and the lattice.
 void choose_paths(fl_solver* s) {
     const fl_params& p = s->prm;
-    s->zmarch = s->lc.zmarch && fl::zmarch_fits(p.lattice, p.ncomp, p.nx, p.ny);
+    // (the isotropic z-marching kernels need two planes or more)
+    s->zmarch = s->lc.zmarch && fl::zmarch_fits(p.lattice, p.ncomp, p.nx, p.ny) && (s->kp.iso == 0 || p.nz >= 2);
     // one-launch step: D3Q19, >= 8 rows per XCD (halo recompute <= 50 %), rows
     // of whole 128-byte lines of the FP64 density arrays, blocks placed on XCD b % 8
     s->fused = s->lc.fused && s->kp.iso == 0 && s->D == 3 && p.ny >= 64 && p.nx % 16 == 0 && p.nz >= 4 &&

@@ -1670,7 +1670,9 @@ hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const v
 hipError_t launch_collide_zmarch_iso(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
                                      const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                      void* fsum_out) {
-    if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1) return hipErrorInvalidValue;
+    // nz >= 2: the prologue reads phi three planes above a z-range's start,
+    // which wrap2 folds into [0, nz) only from two planes on
+    if (!zmarch_fits(lc.lattice, lc.nc, kp.nx, kp.ny) || lc.zlen < 1 || kp.nz < 2) return hipErrorInvalidValue;
     const int tx = kp.nx / kZX, ty = kp.ny / kZY, nzc = (kp.nz + lc.zlen - 1) / lc.zlen;
     const int nb = tx * ty * nzc;
     const int ch = xcd_chunk_for(lc, nb);

@@ -66,7 +66,7 @@ hipError_t launch_collide_zmarch(const LaunchCfg& lc, const KParams& kp, const v
                                  const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                  void* fsum_out);
 // The same with the isotropic stencils (kp.iso): -lap(phi) is computed from
-// phi inside the pass, so no Laplacian pass runs before it.
+// phi inside the pass, so no Laplacian pass runs before it; also needs nz >= 2.
 hipError_t launch_collide_zmarch_iso(const LaunchCfg& lc, const KParams& kp, const void* g, void* gn,
                                      const float* rref, const double* rt, const double* lnf, const void* fsum_in,
                                      void* fsum_out);

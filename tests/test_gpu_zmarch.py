@@ -156,8 +156,9 @@ ISO_CASES = [
     ("ternary_droplets_3d", (64, 8, 7), "fp64", "MRT", 3),
     ("ternary_droplets_3d", (64, 52, 6), "fp32", "MRT", 4),    # 13 tile rows: unequal XCD y-bands
     ("ternary_droplets_3d", (256, 12, 9), "fp32", "MRT", 4),   # four tiles in x, ragged z-range
+    ("ternary_droplets_3d", (64, 8, 2), "fp32", "BGK", 16),    # two planes: z -+ 1 both the other one
     ("binary_slab_3d", (64, 8, 9), "fp32", "BGK", 2),
-    ("binary_slab_3d", (64, 4, 1), "fp64", "BGK", 16),         # one plane: z -+ 1 wrap onto itself
+    ("binary_slab_3d", (64, 4, 1), "fp64", "BGK", 16),         # one plane: the three-pass form runs
     ("binary_slab_3d", (64, 4, 2), "fp32", "MRT", 1),          # two planes, one per workgroup
 ]
 
@@ -192,8 +193,12 @@ def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zl
     b.set_tuning("zmarch=0")
     a.set_state(rho)
     b.set_state(rho)
-    assert list(a.step_timed(1)) == ["k_moments_eos", iso_zmarch_name(w.ncomp, csplit)]
-    assert set(b.step_timed(1)) == {"k_moments_eos", "k_collide_stream", "k_interface_lap"}
+    plain = {"k_moments_eos", "k_collide_stream", "k_interface_lap"}
+    if shape[2] >= 2:
+        assert list(a.step_timed(1)) == ["k_moments_eos", iso_zmarch_name(w.ncomp, csplit)]
+    else:  # one plane: the isotropic z-march needs two, the three-pass form runs
+        assert set(a.step_timed(1)) == plain
+    assert set(b.step_timed(1)) == plain
     a.step(14)
     b.step(14)
     ga, gb = a.populations(), b.populations()
