@@ -376,13 +376,20 @@ def measure_lattice(w, precision, stencil, state, steps, warmup, tuning=None):
     print(f"[bench] {w.name} {w.lattice} {w.shape} nc={w.ncomp} {w.collision} tau={w.tau} {precision} "
           f"{stencil} stencils", file=sys.stderr, flush=True)
     solver.step(warmup)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    solver.step(2)  # two more untimed steps: how long a step takes (first launches are behind)
+    torch.cuda.synchronize()
+    warm_ms = (time.perf_counter() - tw) * 1e3 / 2
     solver.step_timed(0)  # creates the solver's timing events outside the timed region
     torch.cuda.synchronize()
     # the timed region: exactly K steps; HIP events on the solver's stream
-    # around the kernels of every TIMING_EVERY-th step give the per-kernel
-    # launch durations (events on every step would add ~10 us per step)
+    # around the kernels give the per-kernel launch durations: on every step
+    # when a step takes a millisecond or more (the events add ~10 us per
+    # step), else on every TIMING_EVERY-th one
+    every = 1 if warm_ms >= 1.0 else TIMING_EVERY
     t0 = time.perf_counter()
-    kavg, timed_launches = solver.step_timed_every(steps, TIMING_EVERY)
+    kavg, timed_launches = solver.step_timed_every(steps, every)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     print(f"[bench] timed {steps} steps in {wall:.3f} s ({timed_launches} of them with events)",
