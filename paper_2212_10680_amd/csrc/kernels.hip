@@ -1134,9 +1134,11 @@ __global__ __launch_bounds__(256, (kZmarchIsoWaves<NC, P>)) void k_collide_zmarc
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();  // plane z-1's buffer and phi slot z are free
 
+        collide_push_loaded<1, NC, P, MRT>(kp, dm, col + z * plane, x, y, z, in, gn, F, G, Fs, fsum_out, nt != 0);
+        // the plane fills after the pushes: the stores drain while the
+        // Laplacians and chemical potentials are formed
         if (fill) store_fill(z + 2, v);
         if (ring) store_phi(z + 4, fp);
-        collide_push_loaded<1, NC, P, MRT>(kp, dm, col + z * plane, x, y, z, in, gn, F, G, Fs, fsum_out, nt != 0);
         __syncthreads();
     }
 }
