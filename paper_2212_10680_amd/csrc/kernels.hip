@@ -558,9 +558,20 @@ __device__ __forceinline__ void node_velocity(const KParams& kp, double rtot, co
     }
 }
 
+// Which form of the collision a lattice of N_c components in precision P
+// runs (every kernel of one N_c and precision the same, so they agree bit for
+// bit): the pair form (collide_pairs) with FP64 populations, where the
+// three-component isotropic z-march measured 4.33 -> 3.94 ms with it on the
+// 256^3 ternary lattice; the direction-by-direction one (collide) with FP32
+// populations, where the pair form made the three-component split pass
+// slower (2.31 -> 2.43 ms, same box) and left the 128^3 binary z-march and the
+// batched server as they were.
+template <int NC, typename P>
+constexpr bool kPairCollision = sizeof(P) == 8;
+
 // Steps 8-9 of component c at a node: equilibrium, forcing and collision of
 // its populations gv (stored convention, see collide), result in oc.
-template <typename L, typename P, bool MRT>
+template <typename L, typename P, bool MRT, bool PAIRS>
 __device__ __forceinline__ void collide_comp(const KParams& kp, const P (&gv)[L::Q], double rho, double mov,
                                              const double (&u)[3], const P (&F)[3], const P (&G)[3],
                                              P (&oc)[L::Q]) {
@@ -575,10 +586,18 @@ __device__ __forceinline__ void collide_comp(const KParams& kp, const P (&gv)[L:
     if constexpr (sizeof(P) == 8) {
         if (std_form) {
             cs.Gx = cs.Gy = cs.Gz = T(0);  // Guo forcing without the grad rho part
-            collide<L, T, MRT, false, true>(kp, cs, gv, T(mov), oc);
+            if constexpr (PAIRS)
+                collide_pairs<L, T, MRT, false, true>(kp, cs, gv, T(mov), oc);
+            else
+                collide<L, T, MRT, false, true>(kp, cs, gv, T(mov), oc);
         }
     }
-    if (!std_form) collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv, T(mov), oc);
+    if (!std_form) {
+        if constexpr (PAIRS)
+            collide_pairs<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv, T(mov), oc);
+        else
+            collide<L, T, MRT, (sizeof(P) == 4)>(kp, cs, gv, T(mov), oc);
+    }
 }
 
 // Push of component c's post-collision populations to n + e_a of gn
@@ -645,7 +664,7 @@ __device__ __forceinline__ void collide_push_loaded(const KParams& kp, const Dim
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         T (&oc)[Q] = out[kJoint ? c : 0];
-        collide_comp<L, P, MRT>(kp, gv[c], rho[c], mov[c], u, F[c], G[c], oc);
+        collide_comp<L, P, MRT, kPairCollision<NC, P>>(kp, gv[c], rho[c], mov[c], u, F[c], G[c], oc);
         if constexpr (!kJoint) push_comp<L, NC, P>(pg, gn, c, N, oc, nt);
     }
     if constexpr (kJoint) {
@@ -1332,7 +1351,7 @@ __global__ __launch_bounds__(256 * NC) void k_collide_zmarch_iso_cs(
         node_velocity<3, P>(kp, rtot, j, Fs, fprev, u);
         const int n = col + z * plane;
         P oc[Q];
-        collide_comp<L, P, MRT>(kp, gv, rho, mov, u, F, G, oc);
+        collide_comp<L, P, MRT, kPairCollision<NC, P>>(kp, gv, rho, mov, u, F, G, oc);
         push_comp<L, NC, P>(PushGeom<3, NC, P>(dm, n, x, y, z), gn, c, N, oc, nt != 0);
         if (c == 0) {
 #pragma unroll
