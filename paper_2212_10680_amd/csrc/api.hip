@@ -241,8 +241,9 @@ void choose_paths(fl_solver* s) {
 
 // Parses a launch-tuning spec "key=value[,key=value...]" into lc.  Solver
 // keys: k1block, k2block (64..256, multiples of 64), remap, remap2, nt, fused,
-// zmarch, rev, order, csplit (0/1), zlen (1..4096); server keys: serve (256, 512,
-// 1024), serve_cap (>= -1).  Returns false (lc unchanged) for an unknown key
+// zmarch, rev, order, zorder, csplit (0/1), zlen (1..4096), bands, lapbands
+// (0..1024, multiples of 8); server keys: serve (256, 512, 1024), serve_cap
+// (-1..2^20), serve_group (0..2^24).  Returns false (lc unchanged) for an unknown key
 // or an out-of-range value.
 bool parse_tuning(LaunchCfg& lc, const char* spec, bool server) {
     LaunchCfg t = lc;
