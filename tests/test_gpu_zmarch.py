@@ -169,8 +169,13 @@ def iso_zmarch_name(ncomp, csplit):
     return "k_collide_zmarch_iso_cs" if ncomp == 3 and csplit else "k_collide_zmarch_iso"
 
 
-@pytest.mark.parametrize("csplit,zorder", [(1, 0), (1, 1), (0, 0), (0, 1)])
-@pytest.mark.parametrize("wname,shape,precision,coll,zlen", ISO_CASES)
+# csplit selects between the two forms only with three components; the others
+# run the one-thread-per-node form with either value, so they take csplit=1 alone
+ISO_RUNS = [case + (csplit, zorder) for case in ISO_CASES for csplit in (1, 0) for zorder in (0, 1)
+            if csplit == 1 or wl.WORKLOADS[case[0]].ncomp == 3]
+
+
+@pytest.mark.parametrize("wname,shape,precision,coll,zlen,csplit,zorder", ISO_RUNS)
 def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zlen, csplit, zorder):
     """The z-marching kernel with the isotropic stencils (which forms
     -lap(phi) and mu_i in LDS as planes pass) against the one-thread-per-node
@@ -181,8 +186,6 @@ def test_zmarch_isotropic_equals_plain_bitwise(wname, shape, precision, coll, zl
     momenta and forces through LDS (csplit=1); each in both block orders
     (zorder 0: XCD-contiguous chunks, 1: XCD y-bands)."""
     w = wl.WORKLOADS[wname].scaled(shape)
-    if w.ncomp != 3 and csplit == 0:
-        pytest.skip("csplit applies to three components only")
     w.collision = coll
     announce(f"iso zmarch vs plain {wname} {shape} {precision} {coll} zlen={zlen} csplit={csplit} "
              f"zorder={zorder}")
