@@ -478,8 +478,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU (how the lattice would be cut into z-slabs "
-              "over several GPUs is a design, not an implementation); use --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (cutting the lattice into z-slabs over "
+              "several GPUs is designed, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
