@@ -92,10 +92,20 @@ def algorithmic_bytes(w, precision, stencil="axis", lap_pass=None):
     return out
 
 
-def stored_traffic(kernel, nodes, stencil="axis"):
+def _row_precision(row):
+    """Population precision of a traffic row: its own field, else read off the
+    kernel's template arguments."""
+    return row.get("precision") or ("fp64" if "double" in row.get("template", "") else "fp32")
+
+
+def _row_key(row):
+    return (row.get("kernel"), row.get("nodes"), row.get("stencil", "axis"), _row_precision(row))
+
+
+def stored_traffic(kernel, nodes, stencil="axis", precision="fp32"):
     """HBM bytes per launch from the committed PMC counters, if they were taken
-    on the current kernel sources for this kernel, lattice size and stencil
-    (else None)."""
+    on the current kernel sources for this kernel, lattice size, stencil and
+    population precision (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -104,7 +114,7 @@ def stored_traffic(kernel, nodes, stencil="axis"):
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     for k in t.get("kernels", []):
-        if k.get("kernel") == kernel and k.get("nodes") == nodes and k.get("stencil", "axis") == stencil:
+        if _row_key(k) == (kernel, nodes, stencil, precision):
             return k.get("bytes_per_launch")
     return None
 
@@ -306,7 +316,9 @@ def write_traffic(fetch_csv, write_csv, w, stencil, copy_bytes=1 << 30):
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
     `bench.py --copy-calibration`: each counter is scaled by what it reads for
     the 1 GiB device copy in the same run (copy_bytes read and written).
-    Writes profiles/traffic.json and prints a markdown table."""
+    Updates profiles/traffic.json (a row per kernel, lattice size, stencil and
+    population precision; rows taken on other kernel sources are dropped) and
+    prints a markdown table of this run's rows."""
     fetch, write = _pmc_per_dispatch(fetch_csv), _pmc_per_dispatch(write_csv)
 
     def scale(d):
@@ -323,12 +335,29 @@ def write_traffic(fetch_csv, write_csv, w, stencil, copy_bytes=1 << 30):
             continue
         r = float(np.mean(fetch[name])) * 1024 * sf
         wbytes = float(np.mean(write[name])) * 1024 * sw
-        rows.append({"kernel": _kernel_short(name), "template": name.split("(")[0].replace("void ", ""),
-                     "workload": w.name, "nodes": w.nodes, "stencil": stencil, "launches": len(fetch[name]),
-                     "read_bytes": round(r), "write_bytes": round(wbytes), "bytes_per_launch": round(r + wbytes),
-                     "bytes_per_node": round((r + wbytes) / w.nodes, 1)})
+        row = {"kernel": _kernel_short(name), "template": name.split("(")[0].replace("void ", ""),
+               "workload": w.name, "nodes": w.nodes, "stencil": stencil, "launches": len(fetch[name]),
+               "read_bytes": round(r), "write_bytes": round(wbytes), "bytes_per_launch": round(r + wbytes),
+               "bytes_per_node": round((r + wbytes) / w.nodes, 1)}
+        row["precision"] = _row_precision(row)
+        row["scale"] = {"FETCH_SIZE": sf, "WRITE_SIZE": sw}
+        rows.append(row)
+    # rows of other kernels, sizes, stencils or precisions taken on the same
+    # kernel sources are kept; rows from other sources are dropped
+    kept = []
+    try:
+        with open(TRAFFIC_FILE) as f:
+            old = json.load(f)
+        if old.get("kernel_source_hash") == kernel_source_hash():
+            new_keys = {_row_key(r) for r in rows}
+            kept = [r for r in old.get("kernels", []) if _row_key(r) not in new_keys]
+            for r in kept:
+                r.setdefault("precision", _row_precision(r))
+                r.setdefault("scale", old.get("scale"))
+    except (OSError, ValueError):
+        pass
     out = {"kernel_source_hash": kernel_source_hash(), "date": time.strftime("%Y-%m-%d"),
-           "scale": {"FETCH_SIZE": sf, "WRITE_SIZE": sw}, "kernels": rows}
+           "scale": {"FETCH_SIZE": sf, "WRITE_SIZE": sw}, "kernels": kept + rows}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(f"Scale factors from a {copy_bytes >> 20} MiB device copy: FETCH_SIZE x{sf:.4f}, WRITE_SIZE x{sw:.4f}.\n")
@@ -406,7 +435,7 @@ def measure_lattice(w, precision, stencil, state, steps, warmup, tuning=None):
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": stored_traffic(dominant, nodes, stencil),
+        "traffic": stored_traffic(dominant, nodes, stencil, precision),
         "kernel": dominant,
         "kernel_avg_ms": round(avg_ms, 4),
         "algorithmic_bytes_per_node": ab[dominant],

@@ -103,3 +103,34 @@ def test_trace_summary_table(tmp_path, capsys):
     bench.trace_summary(str(p))
     lines = capsys.readouterr().out.strip().splitlines()
     assert lines[-1] == "| `fl::k_moments_eos<1, 3, float>` | 25 | 936.8 | 922.4 | 948.0 | 27.52 |"
+
+
+def test_traffic_rows_per_precision_are_merged(tmp_path, monkeypatch):
+    """A counter run of the FP64 form adds its rows beside the FP32 form's
+    (same kernel name, lattice and stencil); stored_traffic tells them apart by
+    precision, and a later run of one form replaces only that form's rows."""
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    copy = "__amd_rocclr_copyBuffer"
+    k32 = "void fl::k_moments_eos<1, 3, float>(fl::KParams, float const*)"
+    k64 = "void fl::k_moments_eos<1, 3, double>(fl::KParams, double const*)"
+    w = wl.WORKLOADS["ternary_droplets_3d"]
+
+    def run(kname, fetch_kib, tag):
+        fetch, write = tmp_path / f"f{tag}.csv", tmp_path / f"w{tag}.csv"
+        _pmc_csv(fetch, "FETCH_SIZE", [(copy, 1048576.0), (kname, fetch_kib)])
+        _pmc_csv(write, "WRITE_SIZE", [(copy, 1048576.0), (kname, 100.0)])
+        bench.write_traffic(str(fetch), str(write), w, "isotropic")
+
+    run(k32, 1000.0, "a")
+    run(k64, 3000.0, "b")
+    out = json.load(open(tmp_path / "traffic.json"))
+    assert sorted(r["precision"] for r in out["kernels"]) == ["fp32", "fp64"]
+    assert bench.stored_traffic("k_moments_eos", w.nodes, "isotropic", "fp32") == 1100 * 1024
+    assert bench.stored_traffic("k_moments_eos", w.nodes, "isotropic", "fp64") == 3100 * 1024
+    run(k32, 2000.0, "c")
+    assert bench.stored_traffic("k_moments_eos", w.nodes, "isotropic", "fp32") == 2100 * 1024
+    assert bench.stored_traffic("k_moments_eos", w.nodes, "isotropic", "fp64") == 3100 * 1024
+    assert len(json.load(open(tmp_path / "traffic.json"))["kernels"]) == 2
+    # rows taken on other kernel sources are not reported
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.stored_traffic("k_moments_eos", w.nodes, "isotropic", "fp64") is None
