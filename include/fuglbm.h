@@ -164,6 +164,9 @@ int fl_create_ext(const fl_params* p, void* device_mem, size_t bytes, void* hip_
  * reverse order), order (y-major rows inside per-XCD z-slabs), csplit (with
  * the isotropic stencils and N_c = 3: the z-marching collide pass gives each
  * component its own 256 threads, 1 by default; 0 keeps a node in one thread),
+ * mpair (N_c >= 3, FP32 populations, an even node count, the moments pass at
+ * its default 256-thread blocks in plain order: two consecutive nodes per
+ * thread, 1 by default; 0 one node per thread; the same results either way),
  * zorder (block order of the z-marching collide passes: 0 XCD-contiguous
  * chunks, 1 XCD y-bands, all XCDs marching through the same planes; 1 by
  * default with the isotropic stencils and N_c >= 3), zlen (planes per z-marching workgroup, 1..4096), bands and lapbands (XCD-band order of

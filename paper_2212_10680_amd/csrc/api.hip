@@ -241,7 +241,7 @@ void choose_paths(fl_solver* s) {
 
 // Parses a launch-tuning spec "key=value[,key=value...]" into lc.  Solver
 // keys: k1block, k2block (64..256, multiples of 64), remap, remap2, nt, fused,
-// zmarch, rev, order, zorder, csplit (0/1), zlen (1..4096), bands, lapbands
+// zmarch, rev, order, zorder, csplit, mpair (0/1), zlen (1..4096), bands, lapbands
 // (0..1024, multiples of 8); server keys: serve (256, 512, 1024), serve_cap
 // (-1..2^20), serve_group (0..2^24).  Returns false (lc unchanged) for an unknown key
 // or an out-of-range value.
@@ -283,6 +283,8 @@ bool parse_tuning(LaunchCfg& lc, const char* spec, bool server) {
             t.zorder = (int)v;
         } else if (!server && key == "csplit" && flag) {
             t.csplit = v != 0;
+        } else if (!server && key == "mpair" && flag) {
+            t.mpair = v != 0;
         } else if (!server && key == "zlen" && v >= 1 && v <= 4096) {
             t.zlen = (int)v;
         } else if (!server && (key == "bands" || key == "lapbands") && v >= 0 && v <= 1024 && v % 8 == 0) {

@@ -229,6 +229,63 @@ __global__ __launch_bounds__(256) void k_moments_eos(KParams kp, const P* __rest
     if (!node_moments_eos<LAT, NC, P, true>(kp, n, kp.N, g, rref, rt, lnf)) atomicOr(err, 1);
 }
 
+// Steps 1-5 at two consecutive nodes n0, n0 + 1 per thread (N_c >= 3, FP32
+// populations in the component-major layout, N even): each population stream
+// is read 8 bytes per lane, so a wave's load covers four whole 128-byte lines
+// instead of two; the per-node arithmetic is that of node_moments_eos, so the
+// fields are the same bit for bit.
+typedef float fl_f2 __attribute__((ext_vector_type(2)));
+typedef double fl_d2 __attribute__((ext_vector_type(2)));
+
+template <int LAT, int NC>
+__device__ __forceinline__ bool node_fields(const KParams& kp, const float (&gv)[NC][Lat<LAT>::Q],
+                                            const float* __restrict__ rref, int n, size_t N, double (&r)[NC],
+                                            double (&lf)[NC], double& phi) {
+    using L = Lat<LAT>;
+    double rho[NC], mov[NC];
+    densities<L, NC, float>(gv, rref, n, N, rho, mov);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = rho[c] / kp.M[c];
+    const bool ok = eos_lnf<NC>(kp, r, lf, nullptr);
+    phi = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) phi += kp.sk[c] * r[c];
+    return ok;
+}
+
+template <int LAT, int NC>
+__global__ __launch_bounds__(256) void k_moments_eos_pair(KParams kp, const float* __restrict__ g,
+                                                          const float* __restrict__ rref,
+                                                          double* __restrict__ rt, double* __restrict__ lnf,
+                                                          int* __restrict__ err) {
+    static_assert(!kInterleaved<NC>, "component-major layout only");
+    using L = Lat<LAT>;
+    const int n0 = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (n0 >= kp.N) return;  // N even: n0 + 1 < N as well
+    const size_t N = kp.N;
+    float gv0[NC][L::Q], gv1[NC][L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // non-temporal: each line is read once by this pass
+            const fl_f2 v = __builtin_nontemporal_load(
+                reinterpret_cast<const fl_f2*>(pop_base<NC, L::Q>(g, c, a, N) + n0));
+            gv0[c][a] = v.x;
+            gv1[c][a] = v.y;
+        }
+    double r0[NC], r1[NC], lf0[NC], lf1[NC], phi0, phi1;
+    const bool ok0 = node_fields<LAT, NC>(kp, gv0, rref, n0, N, r0, lf0, phi0);
+    const bool ok1 = node_fields<LAT, NC>(kp, gv1, rref, n0 + 1, N, r1, lf1, phi1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        *reinterpret_cast<fl_d2*>(rt + (size_t)c * N + n0) = fl_d2{r0[c], r1[c]};
+        *reinterpret_cast<fl_d2*>(lnf + (size_t)c * N + n0) = fl_d2{lf0[c], lf1[c]};
+    }
+    *reinterpret_cast<fl_d2*>(lnf + (size_t)NC * N + n0) = fl_d2{phi0, phi1};
+    if (!(ok0 && ok1)) atomicOr(err, 1);
+}
+
 // ---------------------------------------------------------------- step 6-9
 // wrap v into [0, m) for |v - [0, m)| <= 2m (stencil offsets of at most 2)
 __device__ __forceinline__ int wrap2(int v, int m) {
@@ -1604,8 +1661,20 @@ hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void
     const int bs = lc.block_k1;
     const int nb = (kp.N + bs - 1) / bs;
     const int ch = xcd_chunk_for(lc, nb);
+    // two nodes per thread where the pass runs at its defaults (256-thread
+    // blocks in plain block order) on an even number of FP32 nodes of >= 3
+    // components; the block-size and block-order keys select the one-node form
+    const bool pair = lc.mpair && lc.nc >= 3 && kp.N % 2 == 0 && bs == 256 &&
+                      ch == 0 && slab_planes(lc, kp) == 0;
     dispatch(lc.lattice, lc.nc, lc.precision, [&](auto latc, auto ncc, auto pt) {
         FL_TYPES;
+        if constexpr (!kInterleaved<NC> && sizeof(P) == 4) {
+            if (pair) {
+                k_moments_eos_pair<LAT, NC><<<(kp.N / 2 + 255) / 256, 256, 0, lc.stream>>>(
+                    kp, (const float*)g, rref, rt, lnf, err);
+                return;
+            }
+        }
         k_moments_eos<LAT, NC, P><<<grid_remapped(nb, ch), bs, 0, lc.stream>>>(
             kp, (const P*)g, rref, rt, lnf, err, ch, slab_planes(lc, kp));
     });

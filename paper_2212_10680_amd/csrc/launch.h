@@ -35,6 +35,8 @@ struct LaunchCfg {
     int bands = 0;          // XCD-band order of the plain collide pass (band_node): row bands, a
                             // multiple of 8; 0 = off
     int bands_lap = 0;      // the same for the interface-Laplacian pass
+    bool mpair = true;      // moments pass with two consecutive nodes per thread where it
+                            // applies (k_moments_eos_pair; fl_set_tuning "mpair=0": one)
 };
 
 hipError_t launch_moments_eos(const LaunchCfg& lc, const KParams& kp, const void* g, const float* rref,
