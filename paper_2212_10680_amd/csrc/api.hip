@@ -173,6 +173,7 @@ void default_launch(fl_solver* s) {
     lc.slab_order = false;
     lc.zlen = 16;
     lc.csplit = true;
+    lc.mpair = true;
     lc.zorder = 0;
     lc.bands = 0;
     lc.bands_lap = 0;

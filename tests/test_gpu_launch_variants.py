@@ -98,7 +98,10 @@ def test_moments_pair_bitwise(wname, shape, precision, stencil):
         rho, u = _sphere_pair(w, shape, min(shape[0], shape[1]) / 3.0), None
     p = F.Params.from_workload(w, precision=precision, stencil=stencil)
     a, b = F.Solver(p), F.Solver(p)
-    b.set_tuning("mpair=0")
+    # the two-node form runs with 256-thread blocks in plain order, the
+    # defaults of the isotropic three-component lattices; set them everywhere
+    a.set_tuning("k1block=256,remap=0")
+    b.set_tuning("k1block=256,remap=0,mpair=0")
     a.set_state(rho, u)
     b.set_state(rho, u)
     a.step(20)
